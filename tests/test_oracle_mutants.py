@@ -1,0 +1,147 @@
+"""Planted mistakes: each test compiles a copy of the oracle with one
+plausible error (a dropped term, a wrong index or order, a transposed
+operand) and checks that the pins used in this suite catch it. The original
+oracle must pass the same pins."""
+import importlib.util
+import json
+import multiprocessing
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+MUTANTS = {
+    "weight_not_multiplied": ("if (sym[i] < 0) w[-sym[i]] += w[r];", "if (sym[i] < 0) w[-sym[i]] += 1;"),
+    "wc_unweighted": ("if (sym[i] >= 0) wc[sym[i]] += w[r];", "if (sym[i] >= 0) wc[sym[i]] += 1;"),
+    "tv_weight_overwritten": ("if (sym[i] < 0) wf[-sym[i]] += wf[r];", "if (sym[i] < 0) wf[-sym[i]] = wf[r];"),
+    "tail_reversed": ("t[want - 1 - got++] = s;", "t[got++] = s;"),
+    "child_head_from_tail": ("h[got++] = head[(size_t)(-s) * m + j];", "h[got++] = tail[(size_t)(-s) * m + j];"),
+    "trigram_operands_swapped": ("(uint64_t)(uint32_t)g[1] << 21 | (uint32_t)g[2];",
+                                 "(uint64_t)(uint32_t)g[2] << 21 | (uint32_t)g[1];"),
+    "sort_ties_descending": ("return x < y ? -1 : (x > y);\n}\nint64_t or_sort",
+                             "return x > y ? -1 : (x < y);\n}\nint64_t or_sort"),
+    "windows_cross_files": ("for (int64_t i = file_off[f]; i + n <= file_off[f + 1]; ++i) keys[m++]",
+                            "for (int64_t i = file_off[f]; i + n <= file_off[F] && i < file_off[f + 1]; ++i) keys[m++]"),
+    "short_child_overlap_kept": ("for (int j = tn - (L - hn); j < tn; ++j)", "for (int j = 0; j < tn; ++j)"),
+    "root_span_weight_dropped": ("if (sym[i] < 0) wf[-sym[i]] += 1;", "if (sym[i] < 0) wf[-sym[i]] = 1;"),
+}
+
+
+def load_variant(tmp_path, name, src_text):
+    d = tmp_path / name
+    d.mkdir()
+    (d / "oracle.c").write_text(src_text)
+    so = d / "liboracle.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(d / "oracle.c")])
+    spec = importlib.util.spec_from_file_location(f"oracle_{name}", os.path.join(ROOT, "oracle", "__init__.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod._LIB_PATH = str(so)
+    mod._lib = None
+    return mod
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        d = json.load(f)
+    g = synth.Grammar(np.array(d["grammar"]["rule_off"], np.int64), np.array(d["grammar"]["sym"], np.int32),
+                      np.array(d["grammar"]["file_off"], np.int64), d["vocab"])
+    return d, g
+
+
+def pins_hold(o) -> bool:
+    """A compact run of the suite's pins: golden values, brute force ==
+    traversal, closed forms."""
+    try:
+        for name in ("e1_sequitur_abcdbc.json", "e2_two_files.json", "e3_head_tail.json"):
+            d, g = gold(name)
+            if "weights" in d and o.weights(g).tolist() != d["weights"]:
+                return False
+            if "word_count" in d and o.traverse_word_count(g).tolist() != d["word_count"]:
+                return False
+            if "sort" in d:
+                ids, cnt = o.sort(g)
+                if ids.tolist() != d["sort"]["id"] or cnt.tolist() != d["sort"]["cnt"]:
+                    return False
+            if "term_vector" in d:
+                off, word, cnt = o.traverse_term_vector(g)
+                if off.tolist() != d["term_vector"]["off"] or cnt.tolist() != d["term_vector"]["cnt"]:
+                    return False
+            for n, key in ((2, "bigrams"), (3, "trigrams")):
+                if key in d:
+                    want = {int(k): v for k, v in d[key].items()}
+                    for fn in (o.traverse_sequence_count, o.brute_sequence_count):
+                        k, c = fn(g, n)
+                        if {int(a): int(b) for a, b in zip(k, c)} != want:
+                            return False
+            if "head_n3" in d:
+                h, t, _ = o.head_tail(g, 3)
+                if any(t[int(r)].tolist() != v for r, v in d["tail_n3"].items()):
+                    return False
+        for seed in range(4):
+            c = synth.random_corpus(seed, 3, 300, 6)
+            g = synth.compress(c.tokens, c.file_off, 6)
+            wc = o.wc_text(c.tokens, 6)
+            if not np.array_equal(o.traverse_word_count(g), wc):
+                return False
+            off, word, cnt = o.traverse_term_vector(g)
+            boff, bword, bcnt = o.tv_text(c.tokens, c.file_off, 6)
+            if not (np.array_equal(off, boff) and np.array_equal(cnt, bcnt)):
+                return False
+            for n in (2, 3):
+                k, cn = o.traverse_sequence_count(g, n)
+                bk, bc = o.sc_text(c.tokens, c.file_off, n, 6)
+                if not (np.array_equal(k, bk) and np.array_equal(cn, bc)):
+                    return False
+                if int(bc.sum()) != int(np.maximum(np.diff(c.file_off) - n + 1, 0).sum()):
+                    return False
+    except (RuntimeError, IndexError, ValueError):
+        return False
+    return True
+
+
+def _child(so_dir, name):
+    import faulthandler
+    faulthandler.disable()
+    mod = importlib.util.module_from_spec(
+        importlib.util.spec_from_file_location(f"oracle_{name}", os.path.join(ROOT, "oracle", "__init__.py")))
+    mod.__spec__.loader.exec_module(mod)
+    mod._LIB_PATH = os.path.join(so_dir, "liboracle.so")
+    mod._lib = None
+    os._exit(0 if pins_hold(mod) else 1)
+
+
+def run_pins(tmp_path, name, src_text) -> bool:
+    """Pins of a variant, in a forked child: a variant that crashes (a planted
+    out-of-bounds write, say) counts as caught."""
+    load_variant(tmp_path, name, src_text)
+    ctx = multiprocessing.get_context("fork")
+    p = ctx.Process(target=_child, args=(str(tmp_path / name), name))
+    p.start()
+    p.join(120)
+    if p.is_alive():
+        p.kill()
+        p.join()
+        return False
+    return p.exitcode == 0
+
+
+def test_original_passes(tmp_path):
+    with open(SRC) as f:
+        assert run_pins(tmp_path, "original", f.read())
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, mutant):
+    with open(SRC) as f:
+        src = f.read()
+    old, new = MUTANTS[mutant]
+    assert src.count(old) == 1, f"mutation site for {mutant} not unique"
+    assert not run_pins(tmp_path, mutant, src.replace(old, new))
