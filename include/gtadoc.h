@@ -1,0 +1,181 @@
+/* gtadoc.h -- exact text analytics directly on Sequitur-compressed text,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The input is text compressed the TADOC way (Background, "TADOC"): words are
+ * dictionary-encoded as integers and a context-free grammar, inferred by
+ * Sequitur, represents the text; rules are nodes of a DAG whose root R0
+ * spells the whole text, with unique splitters between files. The library
+ * answers five analytics without decompressing (Section "Implementation",
+ * the applications kept from the CompressDirect library): word count, sort,
+ * term vector, inverted index and sequence count. Every result is an exact
+ * integer; nothing is approximate.
+ *
+ * Conventions
+ *  - Every function returns an int status: GTADOC_OK (0) or a negative
+ *    GTADOC_ERR_*. No function throws. On error the caller's outputs are left
+ *    untouched and gtadoc_last_error() returns a message (thread-local).
+ *  - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *    Query calls are asynchronous on it unless stated otherwise.
+ *  - Device memory comes from the caller: a context manages one caller-owned
+ *    device buffer (the arena) from which the library sub-allocates grammars,
+ *    scratch and variable-size results (the paper's self-maintained memory
+ *    pool, Section "Data Structures"). The library never calls hipMalloc for
+ *    them.
+ *  - A context is driven by one host thread at a time. Calls on different
+ *    streams are ordered by the context: a call waits for the work of the
+ *    previous call on the same context (an event), so arena memory released
+ *    by one call is never reused while another stream still reads it.
+ *
+ * Grammar encoding (CSR, identical for host and device inputs):
+ *   rule_off int64[num_rules + 1]  body(r) = sym[rule_off[r] .. rule_off[r+1]);
+ *                                  rule 0 is the root; rule_off[0] = 0,
+ *                                  rule_off[num_rules] = num_sym, non-decreasing
+ *   sym      int32[num_sym]        s >= 0: a word id, s < vocab;
+ *                                  s < 0: a reference to rule -s, 1 <= -s < num_rules
+ *                                  (the root cannot be referenced)
+ *   file_off int64[num_files + 1]  file f is the root body [file_off[f], file_off[f+1]):
+ *                                  file_off[0] = 0, file_off[num_files] = length of
+ *                                  the root body, non-decreasing (empty files allowed)
+ *   Every rule other than the root must have a non-empty body and the rule
+ *   graph must be acyclic. Rules that the root does not reach are allowed and
+ *   contribute nothing.
+ */
+#ifndef GTADOC_H
+#define GTADOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define GTADOC_OK 0
+#define GTADOC_ERR_INVALID_ARG (-1)  /* null pointer, bad size, n out of range, vocab <= 0 */
+#define GTADOC_ERR_BAD_GRAMMAR (-2)  /* offsets, ids or file spans violate the encoding above */
+#define GTADOC_ERR_CYCLE (-3)        /* the rule graph has a cycle */
+#define GTADOC_ERR_OOM (-4)          /* the arena cannot hold what the call needs */
+#define GTADOC_ERR_UNSUPPORTED (-5)  /* e.g. n-gram keys that do not fit 64 bits */
+#define GTADOC_ERR_OVERFLOW (-6)     /* an exact hash table could not place a key */
+#define GTADOC_ERR_HIP (-7)          /* a HIP runtime call failed */
+
+/* ---- load flags (exactly one of the first two, optionally BORROW) ---- */
+#define GTADOC_IN_HOST 0x1u    /* inputs are host pointers; copied into the arena */
+#define GTADOC_IN_DEVICE 0x2u  /* inputs are device pointers; copied into the arena */
+#define GTADOC_IN_BORROW 0x4u  /* with IN_DEVICE: keep the caller's device arrays by
+                                  reference instead of copying; they must stay alive
+                                  and unchanged until gtadoc_free_grammar, and sym
+                                  must be 16-byte aligned */
+
+typedef struct gtadoc_ctx_s* gtadoc_ctx;
+typedef struct gtadoc_grammar_s* gtadoc_grammar;
+typedef struct gtadoc_result_s* gtadoc_result;
+
+/* Figures of a loaded grammar. */
+typedef struct {
+  int64_t tokens;      /* T: words of the decompressed text */
+  int64_t symbols;     /* S: symbols over all rule bodies, root included */
+  int64_t rules;       /* R, root included */
+  int64_t files;       /* F */
+  int64_t word_syms;   /* W: word symbols in all bodies */
+  int64_t root_syms;   /* symbols in the root body */
+  int64_t depth;       /* D: number of rule levels below the root (longest path) */
+  int32_t vocab;       /* V */
+  int32_t reserved;
+  uint64_t arena_bytes; /* arena bytes the grammar holds */
+} gtadoc_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context over a caller-owned device buffer `arena` of
+ * `arena_bytes` bytes on the current HIP device (256-byte aligned). The
+ * buffer must outlive the context. Errors: INVALID_ARG (null, too small or
+ * misaligned), HIP. */
+int gtadoc_ctx_create(void* arena, uint64_t arena_bytes, gtadoc_ctx* out);
+
+/* Destroy a context. Grammars and results still alive in it become invalid.
+ * Waits for the context's outstanding work. */
+int gtadoc_ctx_destroy(gtadoc_ctx ctx);
+
+/* Arena bytes in use now, the peak so far, and the capacity. */
+int gtadoc_ctx_usage(gtadoc_ctx ctx, uint64_t* in_use, uint64_t* peak, uint64_t* capacity);
+
+/* ---- grammars --------------------------------------------------------- */
+
+/* Load a compressed text (encoding above) into the context and prepare it
+ * for queries: validation, then the initialization phase of the paper
+ * (Section "Overview", phases; Algorithm "Top-Down Traversal", mask
+ * initialization and traversal): in-degrees of the rules, the level-by-level
+ * topological frontiers of the rule DAG, and the top-down rule weights
+ * (weight(root) = 1, weight(c) = sum over the occurrences of c in body(p) of
+ * weight(p)). Blocks until the load has finished on `stream` (it reads back
+ * the validation status and the level structure). Host inputs may be freed
+ * on return; copied device inputs once the call has returned.
+ * Errors: INVALID_ARG, BAD_GRAMMAR, CYCLE, OOM, HIP. */
+int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t num_rules, const int32_t* sym,
+                        int64_t num_sym, const int64_t* file_off, int64_t num_files, int32_t vocab,
+                        uint32_t flags, void* stream, gtadoc_grammar* out);
+
+int gtadoc_grammar_stats(gtadoc_grammar g, gtadoc_stats* out);
+
+/* Release a grammar's arena memory (after its queued work completes). */
+int gtadoc_free_grammar(gtadoc_grammar g);
+
+/* ---- queries ---------------------------------------------------------- */
+
+/* Word count (Background, "TADOC", word-count walk-through; Algorithm
+ * "Top-Down Traversal", reduce step): counts[w] = number of occurrences of
+ * word w in all files, for w in [0, vocab). `counts` is a caller-owned
+ * device array of vocab uint64, overwritten entirely. Asynchronous.
+ * Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream);
+
+/* Sort (an application of Section "Implementation"): the words with a
+ * nonzero count, ordered by count descending, then word id ascending.
+ * `word_counts` is a device array of vocab uint64 from gtadoc_word_count on
+ * the same grammar, or NULL to compute it inside the call. Writes ids[0..K)
+ * and counts[0..K) (caller-owned device arrays with room for vocab entries)
+ * and K to the device int64 *num. Asynchronous. Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, uint64_t* counts, int64_t* num,
+                void* stream);
+
+/* Term vector (an application of Section "Implementation"; bottom-up
+ * traversal of Section "Fine-Grained Thread-Level Execution Engine"): for
+ * every file, the (word, count) pairs with count > 0, word ascending.
+ * Result arrays: [0] int64 off[F+1], [1] uint32 word[NNZ], [2] uint64 count[NNZ],
+ * file f owning [off[f], off[f+1]). Synchronizes `stream` (sizes are data
+ * dependent). Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream);
+
+/* Inverted index (an application of Section "Implementation"): for every
+ * word, the ascending list of files that contain it. Result arrays:
+ * [0] int64 off[V+1], [1] uint32 file[NNZ]. Synchronizes `stream`.
+ * Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream);
+
+/* Sequence count (Section "Sequence Support"): occurrences of every run of n
+ * consecutive words inside one file (runs never cross files), n in {2, 3}.
+ * Result arrays: [0] uint64 key[U] ascending, [1] uint64 count[U], where the
+ * key packs the n-gram (w0, .., w(n-1)) as w0<<32|w1 for n = 2 and
+ * w0<<42|w1<<21|w2 for n = 3 (ascending keys = lexicographic order).
+ * Synchronizes `stream`. Errors: INVALID_ARG (n), UNSUPPORTED (n = 3 with
+ * vocab > 2^21), OVERFLOW, OOM, HIP. */
+int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream);
+
+/* Array `index` of a result: device pointer (inside the arena), element
+ * count and element size in bytes. The result's sizes are final when the
+ * producing call returns. Errors: INVALID_ARG. */
+int gtadoc_result_array(gtadoc_result res, int index, void** dptr, int64_t* length, int* elem_bytes);
+
+/* Release a result's arena memory. */
+int gtadoc_result_free(gtadoc_result res);
+
+/* Message of the last error on this host thread ("" if none). */
+const char* gtadoc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GTADOC_H */

@@ -1,0 +1,433 @@
+// api.hip -- host runtime of the gtadoc C ABI: contexts over a caller-owned
+// device arena, grammar loading, query entry points, results and errors.
+//
+// The arena plays the role of the paper's self-maintained GPU memory pool
+// (Section "Data Structures"): every device buffer the library needs --
+// grammar copies, initialization-phase products, per-call scratch and
+// variable-size results -- is carved out of one buffer the caller provides,
+// so the library itself never calls hipMalloc.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return fail(GTADOC_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kAlign = 256;
+
+struct Block {
+  uint64_t off = 0, size = 0;
+};
+
+// First-fit allocator over [0, cap) with coalescing of free neighbours.
+class Arena {
+ public:
+  void init(uint64_t cap) {
+    cap_ = cap;
+    free_.clear();
+    free_[0] = cap;
+    in_use_ = peak_ = 0;
+  }
+  bool alloc(uint64_t bytes, Block* out) {
+    const uint64_t need = std::max<uint64_t>(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < need) continue;
+      const uint64_t off = it->first, sz = it->second;
+      free_.erase(it);
+      if (sz > need) free_[off + need] = sz - need;
+      *out = Block{off, need};
+      in_use_ += need;
+      peak_ = std::max(peak_, in_use_);
+      return true;
+    }
+    return false;
+  }
+  void release(const Block& b) {
+    if (b.size == 0) return;
+    in_use_ -= b.size;
+    auto it = free_.emplace(b.off, b.size).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t peak() const { return peak_; }
+  uint64_t cap() const { return cap_; }
+
+ private:
+  uint64_t cap_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+constexpr size_t kPinnedBytes = 64 * 1024;
+
+}  // namespace
+
+struct gtadoc_ctx_s {
+  char* base = nullptr;
+  Arena arena;
+  int device = 0;
+  hipEvent_t done = nullptr;     // end of the most recent call's work
+  hipStream_t last = nullptr;    // stream of that call
+  bool has_done = false;
+  char* pinned = nullptr;        // small pinned host buffer for read-backs
+};
+
+struct gtadoc_grammar_s {
+  gtadoc_ctx ctx = nullptr;
+  std::vector<Block> blocks;
+  gt::DevGrammar d{};
+  gtadoc_stats st{};
+  std::vector<int32_t> level_off;  // host copy, level_off[d] for d = 1..D+1
+};
+
+struct gtadoc_result_s {
+  gtadoc_ctx ctx = nullptr;
+  std::vector<Block> blocks;
+  struct Arr {
+    void* p;
+    int64_t n;
+    int eb;
+  } a[4]{};
+  int na = 0;
+};
+
+namespace {
+
+// Orders a call after the previous call on the same context and owns the
+// call's scratch, which goes back to the arena when the call returns (later
+// calls are ordered after this one's work, so the reuse is safe).
+class Call {
+ public:
+  Call(gtadoc_ctx ctx, void* stream) : ctx_(ctx), s_(static_cast<hipStream_t>(stream)) {}
+  int begin() {
+    if (hipSetDevice(ctx_->device) != hipSuccess) return fail(GTADOC_ERR_HIP, "hipSetDevice failed");
+    if (ctx_->has_done && ctx_->last != s_) HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
+    return GTADOC_OK;
+  }
+  ~Call() {
+    for (const Block& b : scratch_) ctx_->arena.release(b);
+    if (hipEventRecord(ctx_->done, s_) == hipSuccess) {
+      ctx_->last = s_;
+      ctx_->has_done = true;
+    }
+  }
+  // Scratch for this call only.
+  template <typename T>
+  T* scratch(int64_t count) {
+    Block b;
+    if (!ctx_->arena.alloc((uint64_t)std::max<int64_t>(count, 1) * sizeof(T), &b)) return nullptr;
+    scratch_.push_back(b);
+    return reinterpret_cast<T*>(ctx_->base + b.off);
+  }
+  // Memory that outlives the call, recorded in `owner`.
+  template <typename T>
+  T* keep(int64_t count, std::vector<Block>& owner) {
+    Block b;
+    if (!ctx_->arena.alloc((uint64_t)std::max<int64_t>(count, 1) * sizeof(T), &b)) return nullptr;
+    owner.push_back(b);
+    return reinterpret_cast<T*>(ctx_->base + b.off);
+  }
+  hipStream_t stream() const { return s_; }
+
+ private:
+  gtadoc_ctx ctx_;
+  hipStream_t s_;
+  std::vector<Block> scratch_;
+};
+
+int oom(const char* what, uint64_t bytes) {
+  return fail(GTADOC_ERR_OOM, "arena exhausted allocating %s (%llu bytes)", what, (unsigned long long)bytes);
+}
+
+int bitlen(uint64_t x) {
+  int b = 0;
+  while (x) ++b, x >>= 1;
+  return b;
+}
+
+void release_all(gtadoc_ctx ctx, std::vector<Block>& blocks) {
+  for (const Block& b : blocks) ctx->arena.release(b);
+  blocks.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gtadoc_last_error(void) { return g_err.c_str(); }
+
+int gtadoc_ctx_create(void* arena, uint64_t arena_bytes, gtadoc_ctx* out) {
+  if (!arena || !out) return fail(GTADOC_ERR_INVALID_ARG, "null arena or output");
+  if (reinterpret_cast<uintptr_t>(arena) % kAlign != 0) return fail(GTADOC_ERR_INVALID_ARG, "arena not 256-byte aligned");
+  if (arena_bytes < (1u << 16)) return fail(GTADOC_ERR_INVALID_ARG, "arena smaller than 64 KiB");
+  auto* c = new (std::nothrow) gtadoc_ctx_s;
+  if (!c) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  c->base = static_cast<char*>(arena);
+  c->arena.init(arena_bytes);
+  if (hipGetDevice(&c->device) != hipSuccess || hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->pinned), kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    if (c->done) (void)hipEventDestroy(c->done);
+    delete c;
+    return fail(GTADOC_ERR_HIP, "context setup failed");
+  }
+  *out = c;
+  return GTADOC_OK;
+}
+
+int gtadoc_ctx_destroy(gtadoc_ctx ctx) {
+  if (!ctx) return fail(GTADOC_ERR_INVALID_ARG, "null context");
+  if (ctx->has_done) (void)hipEventSynchronize(ctx->done);
+  (void)hipEventDestroy(ctx->done);
+  (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return GTADOC_OK;
+}
+
+int gtadoc_ctx_usage(gtadoc_ctx ctx, uint64_t* in_use, uint64_t* peak, uint64_t* capacity) {
+  if (!ctx) return fail(GTADOC_ERR_INVALID_ARG, "null context");
+  if (in_use) *in_use = ctx->arena.in_use();
+  if (peak) *peak = ctx->arena.peak();
+  if (capacity) *capacity = ctx->arena.cap();
+  return GTADOC_OK;
+}
+
+int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, const int32_t* sym, int64_t S,
+                        const int64_t* file_off, int64_t F, int32_t V, uint32_t flags, void* stream,
+                        gtadoc_grammar* out) {
+  if (!ctx || !out || !rule_off || !file_off || (S > 0 && !sym))
+    return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (R < 1 || R >= INT32_MAX || S < 0 || F < 1 || V <= 0)
+    return fail(GTADOC_ERR_INVALID_ARG, "bad sizes (R=%lld S=%lld F=%lld V=%d)", (long long)R, (long long)S,
+                (long long)F, V);
+  const bool host = flags & GTADOC_IN_HOST, dev = flags & GTADOC_IN_DEVICE, borrow = flags & GTADOC_IN_BORROW;
+  if (host == dev || (borrow && !dev)) return fail(GTADOC_ERR_INVALID_ARG, "flags must be IN_HOST or IN_DEVICE[|BORROW]");
+  if (borrow && reinterpret_cast<uintptr_t>(sym) % 16 != 0)
+    return fail(GTADOC_ERR_INVALID_ARG, "borrowed sym must be 16-byte aligned");
+
+  Call call(ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  auto* g = new (std::nothrow) gtadoc_grammar_s;
+  if (!g) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  g->ctx = ctx;
+  auto bail = [&](int code) {
+    (void)hipStreamSynchronize(s);  // the freed memory may still be in use by queued work
+    release_all(ctx, g->blocks);
+    delete g;
+    return code;
+  };
+
+  gt::DevGrammar& d = g->d;
+  d.R = R;
+  d.S = S;
+  d.F = F;
+  d.V = V;
+  d.ntiles = (S + gt::kTileSyms - 1) / gt::kTileSyms;
+  if (borrow) {
+    d.rule_off = rule_off;
+    d.sym = sym;
+    d.file_off = file_off;
+  } else {
+    int64_t* ro = call.keep<int64_t>(R + 1, g->blocks);
+    int32_t* sy = call.keep<int32_t>(S, g->blocks);
+    int64_t* fo = call.keep<int64_t>(F + 1, g->blocks);
+    if (!ro || !sy || !fo) return bail(oom("grammar copy", 8 * (R + F + 2) + 4 * S));
+    const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(ro, rule_off, 8 * (R + 1), kind, s) != hipSuccess ||
+        (S > 0 && hipMemcpyAsync(sy, sym, 4 * S, kind, s) != hipSuccess) ||
+        hipMemcpyAsync(fo, file_off, 8 * (F + 1), kind, s) != hipSuccess)
+      return bail(fail(GTADOC_ERR_HIP, "grammar copy failed"));
+    d.rule_off = ro;
+    d.sym = sy;
+    d.file_off = fo;
+  }
+  int32_t* tile_rule = call.keep<int32_t>(d.ntiles + 1, g->blocks);
+  d.w = call.keep<uint64_t>(R, g->blocks);
+  d.level_rule = call.keep<int32_t>(std::max<int64_t>(R - 1, 1), g->blocks);
+  d.level_off = call.keep<int32_t>(R + 2, g->blocks);
+  int32_t* pend = call.scratch<int32_t>(R);
+  int32_t* level_cnt = call.scratch<int32_t>(R + 2);
+  auto* lc = call.scratch<gt::LoadCounters>(1);
+  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc)
+    return bail(oom("initialization-phase buffers", 28 * (uint64_t)R));
+  d.tile_rule = tile_rule;
+
+  auto* pc = reinterpret_cast<gt::LoadCounters*>(ctx->pinned);
+  auto hip_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+      fail(GTADOC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+      return false;
+    }
+    return true;
+  };
+  // phase 1: offsets and file spans (must hold before any kernel indexes by them)
+  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
+      !hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
+      !hip_ok(gt::launch_check_files(d.file_off, F, d.rule_off, lc, s), "check_files") ||
+      !hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read status") ||
+      !hip_ok(hipStreamSynchronize(s), "sync"))
+    return bail(GTADOC_ERR_HIP);
+  if (pc->status)
+    return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s%s",
+                     (pc->status & gt::ST_BAD_OFFSETS) ? "rule offsets not monotone in [0, S]; " : "",
+                     (pc->status & gt::ST_EMPTY_BODY) ? "empty non-root rule body; " : "",
+                     (pc->status & gt::ST_BAD_FILES) ? "file spans do not tile the root body" : ""));
+  // phase 2: symbols, in-degrees, levels and weights
+  if (!hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill") || !hip_ok(gt::launch_fill_i32(pend, R, 0, s), "fill") ||
+      !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
+      !hip_ok(gt::launch_scan_symbols(d, pend, lc, s), "scan_symbols") ||
+      !hip_ok(gt::launch_levels(d, pend, level_cnt, lc, ctx->device, s), "levels") ||
+      !hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
+      !hip_ok(hipStreamSynchronize(s), "sync"))
+    return bail(GTADOC_ERR_HIP);
+  if (pc->status)
+    return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s",
+                     (pc->status & gt::ST_BAD_WORD) ? "word id >= vocab; " : "",
+                     (pc->status & gt::ST_BAD_REF) ? "rule reference outside [1, R)" : ""));
+  if (pc->placed != R - 1)
+    return bail(fail(GTADOC_ERR_CYCLE, "rule graph has a cycle (%lld of %lld rules ordered)", (long long)pc->placed,
+                     (long long)(R - 1)));
+  const int32_t D = pc->depth;
+  g->level_off.assign((size_t)D + 2, 0);
+  if (D > 0) {
+    if (!hip_ok(hipMemcpyAsync(g->level_off.data(), d.level_off, sizeof(int32_t) * (D + 2), hipMemcpyDeviceToHost, s),
+                "read levels") ||
+        !hip_ok(hipStreamSynchronize(s), "sync"))
+      return bail(GTADOC_ERR_HIP);
+  }
+  gtadoc_stats& st = g->st;
+  st.tokens = (int64_t)(pc->tokens + pc->root_words);
+  st.symbols = S;
+  st.rules = R;
+  st.files = F;
+  st.word_syms = (int64_t)pc->word_syms;
+  st.root_syms = 0;
+  st.depth = D;
+  st.vocab = V;
+  uint64_t bytes = 0;
+  for (const Block& b : g->blocks) bytes += b.size;
+  st.arena_bytes = bytes;
+  *out = g;
+  return GTADOC_OK;
+}
+
+int gtadoc_grammar_stats(gtadoc_grammar g, gtadoc_stats* out) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  *out = g->st;
+  return GTADOC_OK;
+}
+
+int gtadoc_free_grammar(gtadoc_grammar g) {
+  if (!g) return fail(GTADOC_ERR_INVALID_ARG, "null grammar");
+  release_all(g->ctx, g->blocks);
+  delete g;
+  return GTADOC_OK;
+}
+
+int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream) {
+  if (!g || !counts) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  HIP_TRY(gt::launch_word_count(g->d, counts, call.stream()));
+  return GTADOC_OK;
+}
+
+int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, uint64_t* counts, int64_t* num,
+                void* stream) {
+  if (!g || !ids || !counts || !num) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  const int32_t V = g->d.V;
+  if (!word_counts) {
+    uint64_t* wc = call.scratch<uint64_t>(V);
+    if (!wc) return oom("word counts", 8ull * V);
+    HIP_TRY(gt::launch_word_count(g->d, wc, s));
+    word_counts = wc;
+  }
+  gt::SortScratch sc{};
+  sc.key[0] = call.scratch<uint64_t>(V);
+  sc.key[1] = call.scratch<uint64_t>(V);
+  sc.val[0] = call.scratch<uint32_t>(V);
+  sc.val[1] = call.scratch<uint32_t>(V);
+  sc.hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(V));
+  sc.num = call.scratch<int64_t>(1);
+  sc.capacity = V;
+  if (!sc.key[0] || !sc.key[1] || !sc.val[0] || !sc.val[1] || !sc.hist || !sc.num) return oom("sort scratch", 24ull * V);
+  const int key_bytes = std::max(1, (bitlen((uint64_t)g->st.tokens) + 7) / 8);
+  HIP_TRY(gt::launch_sort_by_count(word_counts, V, key_bytes, sc, ids, counts, num, s));
+  return GTADOC_OK;
+}
+
+int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  (void)stream;
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  return fail(GTADOC_ERR_UNSUPPORTED, "term vector: not available in this build");
+}
+
+int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  (void)stream;
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  return fail(GTADOC_ERR_UNSUPPORTED, "inverted index: not available in this build");
+}
+
+int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
+  (void)stream;
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (n < 2 || n > 3) return fail(GTADOC_ERR_INVALID_ARG, "n must be 2 or 3");
+  return fail(GTADOC_ERR_UNSUPPORTED, "sequence count: not available in this build");
+}
+
+int gtadoc_result_array(gtadoc_result res, int index, void** dptr, int64_t* length, int* elem_bytes) {
+  if (!res || index < 0 || index >= res->na) return fail(GTADOC_ERR_INVALID_ARG, "bad result or index");
+  if (dptr) *dptr = res->a[index].p;
+  if (length) *length = res->a[index].n;
+  if (elem_bytes) *elem_bytes = res->a[index].eb;
+  return GTADOC_OK;
+}
+
+int gtadoc_result_free(gtadoc_result res) {
+  if (!res) return fail(GTADOC_ERR_INVALID_ARG, "null result");
+  release_all(res->ctx, res->blocks);
+  delete res;
+  return GTADOC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// internal.h -- shared declarations of the gtadoc library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/gtadoc.h"
+
+namespace gt {
+
+// ---------------------------------------------------------------------------
+// Launch geometry
+// ---------------------------------------------------------------------------
+// Position-parallel passes over the rule bodies work on tiles of kTileSyms
+// consecutive symbols, one 256-thread workgroup per tile, 16 consecutive
+// symbols per thread (four 16-byte loads).
+constexpr int kTileSyms = 4096;
+constexpr int kTileThreads = 256;
+constexpr int kPerThread = kTileSyms / kTileThreads;
+// LDS slots for a tile's rule offsets: at most kTileSyms + 2 rules overlap a tile.
+constexpr int kTileRuleSlots = kTileSyms + 4;
+
+// Bits of the validation status word.
+enum : uint32_t {
+  ST_BAD_OFFSETS = 1u,   // rule_off not monotone / not [0, S]
+  ST_EMPTY_BODY = 2u,    // a non-root rule has an empty body
+  ST_BAD_FILES = 4u,     // file spans do not tile the root body
+  ST_BAD_WORD = 8u,      // word id >= vocab
+  ST_BAD_REF = 16u,      // rule reference outside [1, R)
+};
+
+// Device view of a loaded grammar and its initialization-phase products.
+struct DevGrammar {
+  const int64_t* rule_off;   // [R+1]
+  const int32_t* sym;        // [S]
+  const int64_t* file_off;   // [F+1]
+  int64_t R, S, F;
+  int32_t V;
+  int64_t ntiles;            // ceil(S / kTileSyms)
+  const int32_t* tile_rule;  // [ntiles+1]: rule holding the first symbol of each tile; [ntiles] = R-1
+  uint64_t* w;               // [R] top-down weights, w[0] = 1
+  int32_t* level_rule;       // [R-1] rules grouped by level (level 1 first)
+  int32_t* level_off;        // [D+2] level d occupies level_rule[level_off[d] .. level_off[d+1]), d >= 1
+};
+
+// Load-phase scalars written by the kernels and read back once.
+struct LoadCounters {
+  uint32_t status;       // ST_* bits
+  int32_t depth;         // number of levels
+  int32_t placed;        // rules placed in levels (R-1 unless there is a cycle)
+  int32_t pad;
+  uint64_t tokens;       // T
+  uint64_t word_syms;    // W
+  uint64_t root_words;   // words directly in the root body
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each returns the launch status)
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// load phase
+hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int32_t* tile_rule, int64_t ntiles,
+                              LoadCounters* lc, hipStream_t s);
+hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc,
+                              hipStream_t s);
+hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s);
+hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, int device,
+                         hipStream_t s);
+
+// word count and sort
+hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);
+struct SortScratch {
+  uint64_t* key[2];
+  uint32_t* val[2];
+  uint32_t* hist;       // [256 * nblocks]
+  int64_t* num;         // device K
+  int64_t capacity;
+};
+int64_t sort_scratch_hist_entries(int64_t n);
+hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,
+                                uint64_t* cnt_out, int64_t* num_out, hipStream_t s);
+
+}  // namespace gt

@@ -1,0 +1,225 @@
+"""Python binding of libgtadoc (ctypes). Argument marshalling only: every
+step of every query runs in the library's HIP kernels. torch provides the
+device memory (the arena and the output tensors) and the streams.
+
+Loading fails loudly when the HIP library has not been built; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgtadoc.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "gtadoc.h")
+
+OK = 0
+ERR_INVALID_ARG, ERR_BAD_GRAMMAR, ERR_CYCLE, ERR_OOM, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_HIP = range(-1, -8, -1)
+IN_HOST, IN_DEVICE, IN_BORROW = 0x1, 0x2, 0x4
+_NAMES = {-1: "INVALID_ARG", -2: "BAD_GRAMMAR", -3: "CYCLE", -4: "OOM", -5: "UNSUPPORTED", -6: "OVERFLOW", -7: "HIP"}
+
+
+class GtadocError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"gtadoc error {_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("tokens", ctypes.c_int64), ("symbols", ctypes.c_int64), ("rules", ctypes.c_int64),
+                ("files", ctypes.c_int64), ("word_syms", ctypes.c_int64), ("root_syms", ctypes.c_int64),
+                ("depth", ctypes.c_int64), ("vocab", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+_vp, _i64, _i32, _u32, _u64, _int = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                     ctypes.c_uint64, ctypes.c_int)
+
+EXPORTS = {
+    "gtadoc_ctx_create": [_vp, _u64, _vp],
+    "gtadoc_ctx_destroy": [_vp],
+    "gtadoc_ctx_usage": [_vp, _vp, _vp, _vp],
+    "gtadoc_load_grammar": [_vp, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _u32, _vp, _vp],
+    "gtadoc_grammar_stats": [_vp, _vp],
+    "gtadoc_free_grammar": [_vp],
+    "gtadoc_word_count": [_vp, _vp, _vp],
+    "gtadoc_sort": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "gtadoc_term_vector": [_vp, _vp, _vp],
+    "gtadoc_inverted_index": [_vp, _vp, _vp],
+    "gtadoc_sequence_count": [_vp, _int, _vp, _vp],
+    "gtadoc_result_array": [_vp, _int, _vp, _vp, _vp],
+    "gtadoc_result_free": [_vp],
+    "gtadoc_last_error": [],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library. Raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2106_06889_amd.build)")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, args in EXPORTS.items():
+            fn = getattr(l, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "gtadoc_last_error" else ctypes.c_int
+        _lib = l
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise GtadocError(rc, lib().gtadoc_last_error().decode())
+
+
+def _stream_ptr(stream) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_tensor(ptr: int, n: int, elem_bytes: int, owner: torch.Tensor) -> torch.Tensor:
+    """A view of n elements at device address ptr inside `owner` (the arena)."""
+    off = ptr - owner.data_ptr()
+    dtype = {4: torch.int32, 8: torch.int64}[elem_bytes]
+    if n == 0:
+        return torch.empty(0, dtype=dtype, device=owner.device)
+    return owner[off:off + n * elem_bytes].view(dtype)
+
+
+class Context:
+    """A gtadoc context over a torch-owned device arena."""
+
+    def __init__(self, arena_bytes: int, device: int | str | torch.device = "cuda"):
+        self.device = torch.device(device) if not isinstance(device, int) else torch.device("cuda", device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().gtadoc_ctx_create(self.arena.data_ptr(), int(arena_bytes), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().gtadoc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def usage(self) -> tuple[int, int, int]:
+        a, b, c = _u64(), _u64(), _u64()
+        _check(lib().gtadoc_ctx_usage(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def load(self, rule_off, sym, file_off, vocab: int, stream=None, borrow: bool = False) -> "Grammar":
+        """Load a grammar from numpy arrays (host) or torch device tensors."""
+        keep = ()
+        if isinstance(sym, torch.Tensor):
+            rule_off = rule_off.to(torch.int64).contiguous()
+            sym = sym.to(torch.int32).contiguous()
+            file_off = file_off.to(torch.int64).contiguous()
+            flags = IN_DEVICE | (IN_BORROW if borrow else 0)
+            ptrs = (rule_off.data_ptr(), sym.data_ptr() if sym.numel() else None, file_off.data_ptr())
+            keep = (rule_off, sym, file_off) if borrow else ()
+        else:
+            rule_off = np.ascontiguousarray(rule_off, dtype=np.int64)
+            sym = np.ascontiguousarray(sym, dtype=np.int32)
+            file_off = np.ascontiguousarray(file_off, dtype=np.int64)
+            flags = IN_HOST
+            ptrs = (rule_off.ctypes.data, sym.ctypes.data if sym.size else None, file_off.ctypes.data)
+        R, S, F = len(rule_off) - 1, len(sym), len(file_off) - 1
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().gtadoc_load_grammar(self.handle, ptrs[0], R, ptrs[1], S, ptrs[2], F, int(vocab), flags,
+                                             _stream_ptr(stream), ctypes.byref(h)))
+        return Grammar(self, h, keep)
+
+
+@dataclass
+class Result:
+    arrays: list
+    handle: object
+    ctx: Context
+
+    def free(self):
+        if self.handle:
+            lib().gtadoc_result_free(self.handle)
+            self.handle = None
+
+
+class Grammar:
+    def __init__(self, ctx: Context, handle, keep=()):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+        st = Stats()
+        _check(lib().gtadoc_grammar_stats(handle, ctypes.byref(st)))
+        self.stats = st.as_dict()
+        self.vocab = st.vocab
+
+    def free(self):
+        if self.handle:
+            lib().gtadoc_free_grammar(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def word_count(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """uint64 counts as an int64 tensor of vocab entries (bit pattern = uint64)."""
+        if out is None:
+            out = torch.empty(self.vocab, dtype=torch.int64, device=self.ctx.device)
+        assert out.dtype == torch.int64 and out.numel() == self.vocab and out.is_contiguous()
+        _check(lib().gtadoc_word_count(self.handle, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def sort(self, word_counts: torch.Tensor | None = None, stream=None):
+        """(ids int32[K], counts int64[K]) device tensors, count desc then id asc."""
+        V = self.vocab
+        ids = torch.empty(V, dtype=torch.int32, device=self.ctx.device)
+        cnt = torch.empty(V, dtype=torch.int64, device=self.ctx.device)
+        num = torch.empty(1, dtype=torch.int64, device=self.ctx.device)
+        wc = word_counts.data_ptr() if word_counts is not None else None
+        _check(lib().gtadoc_sort(self.handle, wc, ids.data_ptr(), cnt.data_ptr(), num.data_ptr(),
+                                 _stream_ptr(stream)))
+        return ids, cnt, num
+
+    def _result(self, fn, *args, stream=None) -> Result:
+        h = _vp()
+        _check(fn(self.handle, *args, ctypes.byref(h), _stream_ptr(stream)))
+        arrays = []
+        i = 0
+        while True:
+            p, n, eb = _vp(), _i64(), _int()
+            if lib().gtadoc_result_array(h, i, ctypes.byref(p), ctypes.byref(n), ctypes.byref(eb)) != OK:
+                break
+            arrays.append(_dev_tensor(p.value or self.ctx.arena.data_ptr(), n.value, eb.value, self.ctx.arena))
+            i += 1
+        return Result(arrays, h, self.ctx)
+
+    def term_vector(self, stream=None) -> Result:
+        return self._result(lib().gtadoc_term_vector, stream=stream)
+
+    def inverted_index(self, stream=None) -> Result:
+        return self._result(lib().gtadoc_inverted_index, stream=stream)
+
+    def sequence_count(self, n: int, stream=None) -> Result:
+        return self._result(lib().gtadoc_sequence_count, n, stream=stream)
+
+
+def to_u64(t: torch.Tensor) -> np.ndarray:
+    """Host copy of an int64 device tensor holding uint64 values."""
+    return t.cpu().numpy().view(np.uint64)

@@ -1,0 +1,148 @@
+"""GPU parity: word count and sort through the C ABI against the oracle,
+bit-exact (uint64 counts; the sort order is total, so unique)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2106_06889_amd as gt
+    assert torch.cuda.is_available()
+    c = gt.Context(2 << 30)
+    yield c
+    c.close()
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        d = json.load(f)
+    return synth.Grammar(np.array(d["grammar"]["rule_off"], np.int64), np.array(d["grammar"]["sym"], np.int32),
+                         np.array(d["grammar"]["file_off"], np.int64), d["vocab"])
+
+
+def check_wc_sort(ctx, g, expect_tokens=None):
+    import paper_2106_06889_amd as gt
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        want = oracle.traverse_word_count(g)
+        got = gt.to_u64(G.word_count())
+        assert np.array_equal(got, want)
+        assert G.stats["tokens"] == int(want.sum())
+        if expect_tokens is not None:
+            assert G.stats["tokens"] == expect_tokens
+        wid, wcnt = oracle.sort_counts(want)
+        ids, cnt, num = G.sort()
+        k = int(num.item())
+        assert k == len(wid)
+        assert np.array_equal(ids[:k].cpu().numpy().view(np.uint32), wid)
+        assert np.array_equal(gt.to_u64(cnt[:k]), wcnt)
+        # sort from precomputed counts gives the same
+        ids2, cnt2, num2 = G.sort(word_counts=G.word_count())
+        assert int(num2.item()) == k and np.array_equal(ids2[:k].cpu().numpy(), ids[:k].cpu().numpy())
+        return G.stats
+    finally:
+        G.free()
+
+
+@pytest.mark.parametrize("name", ["e1_sequitur_abcdbc.json", "e2_two_files.json", "e3_head_tail.json"])
+def test_golden(ctx, name):
+    g = gold(name)
+    st = check_wc_sort(ctx, g)
+    assert st["depth"] == {"e1_sequitur_abcdbc.json": 2, "e2_two_files.json": 2, "e3_head_tail.json": 1}[name]
+
+
+def test_root_only_and_empty(ctx):
+    tok = np.array([3, 1, 3, 0, 2, 3], np.int32)
+    g = synth.Grammar(np.array([0, 6], np.int64), tok, np.array([0, 2, 2, 6], np.int64), 5)
+    assert check_wc_sort(ctx, g)["depth"] == 0
+    empty = synth.Grammar(np.array([0, 0], np.int64), np.zeros(0, np.int32), np.array([0, 0], np.int64), 3)
+    check_wc_sort(ctx, empty, expect_tokens=0)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_corpora(ctx, seed):
+    c = synth.random_corpus(seed, 1 + seed % 4, 3000, [3, 20, 400][seed % 3])
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    check_wc_sort(ctx, g, expect_tokens=len(c.tokens))
+
+
+def test_unreachable_rule_contributes_nothing(ctx):
+    # rule 2 is never referenced; rule 3 only from rule 2
+    g = synth.Grammar(np.array([0, 3, 5, 7, 9], np.int64), np.array([-1, 0, -1, 1, 2, -3, 0, 4, 4], np.int32),
+                      np.array([0, 3], np.int64), 5)
+    check_wc_sort(ctx, g)
+
+
+def test_wc_200k_full(ctx):
+    c, g = synth.workload("wc-200k")
+    st = check_wc_sort(ctx, g, expect_tokens=len(c.tokens))
+    assert np.array_equal(oracle.traverse_word_count(g), oracle.wc_text(c.tokens, c.vocab))
+    assert st["rules"] == g.num_rules
+
+
+def test_wc_100m_recipe_scaled(ctx):
+    c, g = synth.workload("wc-100m", scale=0.03)
+    check_wc_sort(ctx, g, expect_tokens=len(c.tokens))
+
+
+def test_tile_boundaries(ctx):
+    """Bodies that straddle many tile boundaries: a long non-root rule and a
+    root longer than several tiles, with a ragged tail."""
+    rng = np.random.default_rng(7)
+    body1 = rng.integers(0, 50, size=9000).astype(np.int32)          # rule 1: > 2 tiles of words
+    root = np.where(rng.random(13001) < 0.1, -1, rng.integers(0, 50, size=13001)).astype(np.int32)
+    sym = np.concatenate([root, body1])
+    g = synth.Grammar(np.array([0, len(root), len(sym)], np.int64), sym, np.array([0, 5000, len(root)], np.int64), 50)
+    check_wc_sort(ctx, g)
+
+
+def test_rejects_bad_grammars(ctx):
+    import paper_2106_06889_amd as gt
+    V = 4
+    cases = {
+        "word>=V": (np.array([0, 2, 4], np.int64), np.array([-1, -1, 0, 4], np.int32), np.array([0, 2], np.int64), gt.ERR_BAD_GRAMMAR),
+        "ref>=R": (np.array([0, 2, 4], np.int64), np.array([-1, -3, 0, 1], np.int32), np.array([0, 2], np.int64), gt.ERR_BAD_GRAMMAR),
+        "int32 min": (np.array([0, 2, 4], np.int64), np.array([-1, -2**31, 0, 1], np.int32), np.array([0, 2], np.int64), gt.ERR_BAD_GRAMMAR),
+        "offsets": (np.array([0, 3, 2], np.int64), np.array([-1, -1, 0, 1], np.int32)[:2], np.array([0, 3], np.int64), gt.ERR_BAD_GRAMMAR),
+        "empty body": (np.array([0, 2, 2], np.int64), np.array([0, 1], np.int32), np.array([0, 2], np.int64), gt.ERR_BAD_GRAMMAR),
+        "spans": (np.array([0, 2, 4], np.int64), np.array([-1, -1, 0, 1], np.int32), np.array([0, 1], np.int64), gt.ERR_BAD_GRAMMAR),
+        "cycle": (np.array([0, 1, 3, 5], np.int64), np.array([-1, 0, -2, -1, 1], np.int32), np.array([0, 1], np.int64), gt.ERR_CYCLE),
+    }
+    before = ctx.usage()[0]
+    for name, (ro, sym, fo, code) in cases.items():
+        with pytest.raises(gt.GtadocError) as e:
+            ctx.load(ro, sym, fo, V)
+        assert e.value.code == code, name
+    assert ctx.usage()[0] == before  # nothing leaked
+
+
+def test_arena_too_small():
+    import paper_2106_06889_amd as gt
+    small = gt.Context(1 << 16)
+    c, g = synth.workload("wc-200k")
+    with pytest.raises(gt.GtadocError) as e:
+        small.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    assert e.value.code == gt.ERR_OOM
+    small.close()
+
+
+def test_device_and_borrowed_inputs(ctx):
+    import torch
+    import paper_2106_06889_amd as gt
+    c, g = synth.workload("wc-200k", scale=0.5)
+    want = oracle.traverse_word_count(g)
+    dev = [torch.from_numpy(a).cuda() for a in (g.rule_off, g.sym, g.file_off)]
+    for borrow in (False, True):
+        G = ctx.load(*dev, g.vocab, borrow=borrow)
+        assert np.array_equal(gt.to_u64(G.word_count()), want)
+        G.free()
