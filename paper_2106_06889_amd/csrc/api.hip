@@ -258,6 +258,10 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   d.F = F;
   d.V = V;
   d.ntiles = (S + gt::kTileSyms - 1) / gt::kTileSyms;
+  d.nblk = (S + gt::kBlockSyms - 1) / gt::kBlockSyms;
+  d.nslot = gt::kXcds * ((d.nblk + gt::kXcds - 1) / gt::kXcds);
+  d.wc_nb = ((int64_t)V <= (int64_t)gt::kWcBucket * gt::kWcMaxBuckets) ? (int32_t)((V + gt::kWcBucket - 1) / gt::kWcBucket) : 0;
+  d.rc_nb = (R <= (int64_t)gt::kRcBucket * gt::kRcMaxBuckets) ? (int32_t)((R + gt::kRcBucket - 1) / gt::kRcBucket) : 0;
   if (borrow) {
     d.rule_off = rule_off;
     d.sym = sym;
@@ -280,11 +284,19 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   d.w = call.keep<uint64_t>(R, g->blocks);
   d.level_rule = call.keep<int32_t>(std::max<int64_t>(R - 1, 1), g->blocks);
   d.level_off = call.keep<int32_t>(R + 2, g->blocks);
+  const int64_t n_wc_off = (int64_t)d.wc_nb * d.nslot;
+  const int64_t n_rc_off = (int64_t)d.rc_nb * d.nslot;
+  d.wc_off = d.wc_nb ? call.keep<uint32_t>(n_wc_off, g->blocks) : nullptr;
+  d.rc_off = d.rc_nb ? call.scratch<uint32_t>(n_rc_off) : nullptr;
   int32_t* pend = call.scratch<int32_t>(R);
   int32_t* level_cnt = call.scratch<int32_t>(R + 2);
   auto* lc = call.scratch<gt::LoadCounters>(1);
-  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc)
-    return bail(oom("initialization-phase buffers", 28 * (uint64_t)R));
+  const int64_t nbR = (R + 4095) / 4096;
+  uint32_t* sums = call.scratch<uint32_t>(
+      std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off), nbR + gt::scan_scratch_entries(nbR)}));
+  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc || !sums ||
+      (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
+    return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));
   d.tile_rule = tile_rule;
 
   auto* pc = reinterpret_cast<gt::LoadCounters*>(ctx->pinned);
@@ -308,10 +320,25 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
                      (pc->status & gt::ST_EMPTY_BODY) ? "empty non-root rule body; " : "",
                      (pc->status & gt::ST_BAD_FILES) ? "file spans do not tile the root body" : ""));
   // phase 2: symbols, in-degrees, levels and weights
-  if (!hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill") || !hip_ok(gt::launch_fill_i32(pend, R, 0, s), "fill") ||
-      !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
+  const bool atomic_degrees = d.rc_nb == 0;
+  if (!hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
+      (atomic_degrees && (!hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill") ||
+                          !hip_ok(gt::launch_fill_i32(pend, R, 0, s), "fill"))) ||
+      (n_wc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
+      (n_rc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
       !hip_ok(gt::launch_scan_symbols(d, pend, lc, s), "scan_symbols") ||
-      !hip_ok(gt::launch_levels(d, pend, level_cnt, lc, ctx->device, s), "levels") ||
+      (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
+      (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
+      (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, 1, 1, s), "fill")))
+    return bail(GTADOC_ERR_HIP);
+  if (!atomic_degrees) {
+    // one entry per rule reference: at most S of them (the exact count stays on the device)
+    uint16_t* ref_entries = call.scratch<uint16_t>(S);
+    if (!ref_entries) return bail(oom("reference entries", 2 * (uint64_t)S));
+    if (!hip_ok(gt::launch_in_degrees(d, pend, ref_entries, &lc->rc_entries, s), "in_degrees"))
+      return bail(GTADOC_ERR_HIP);
+  }
+  if (!hip_ok(gt::launch_levels(d, pend, level_cnt, lc, sums, ctx->device, s), "levels") ||
       !hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
@@ -319,6 +346,9 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s",
                      (pc->status & gt::ST_BAD_WORD) ? "word id >= vocab; " : "",
                      (pc->status & gt::ST_BAD_REF) ? "rule reference outside [1, R)" : ""));
+  if (d.wc_nb && pc->wc_entries != (int64_t)pc->word_syms)
+    return bail(fail(GTADOC_ERR_HIP, "internal: word bucket histogram %lld != word symbols %llu",
+                     (long long)pc->wc_entries, (unsigned long long)pc->word_syms));
   if (pc->placed != R - 1)
     return bail(fail(GTADOC_ERR_CYCLE, "rule graph has a cycle (%lld of %lld rules ordered)", (long long)pc->placed,
                      (long long)(R - 1)));
@@ -359,13 +389,35 @@ int gtadoc_free_grammar(gtadoc_grammar g) {
   return GTADOC_OK;
 }
 
+namespace {
+// Word count into `counts` on the call's stream: the bucketed on-chip
+// reduction when the vocabulary fits the bucket table and every weight fits
+// the packed entry (weights never exceed the token count), else direct atomics.
+int word_count_into(gtadoc_grammar g, Call& call, uint64_t* counts) {
+  const gt::DevGrammar& d = g->d;
+  const int64_t W = g->st.word_syms;
+  hipStream_t s = call.stream();
+  if (W == 0) {
+    HIP_TRY(gt::launch_fill_u64(counts, d.V, 0, s));
+    return GTADOC_OK;
+  }
+  if (d.wc_nb > 0 && (uint64_t)g->st.tokens < (1ull << (64 - gt::kWcBits))) {
+    uint64_t* entries = call.scratch<uint64_t>(W);
+    if (!entries) return oom("word entries", 8ull * W);
+    HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, s));
+    return GTADOC_OK;
+  }
+  HIP_TRY(gt::launch_word_count(d, counts, s));
+  return GTADOC_OK;
+}
+}  // namespace
+
 int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream) {
   if (!g || !counts) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   Call call(g->ctx, stream);
   int rc = call.begin();
   if (rc) return rc;
-  HIP_TRY(gt::launch_word_count(g->d, counts, call.stream()));
-  return GTADOC_OK;
+  return word_count_into(g, call, counts);
 }
 
 int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, uint64_t* counts, int64_t* num,
@@ -379,7 +431,8 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
   if (!word_counts) {
     uint64_t* wc = call.scratch<uint64_t>(V);
     if (!wc) return oom("word counts", 8ull * V);
-    HIP_TRY(gt::launch_word_count(g->d, wc, s));
+    rc = word_count_into(g, call, wc);
+    if (rc) return rc;
     word_counts = wc;
   }
   gt::SortScratch sc{};

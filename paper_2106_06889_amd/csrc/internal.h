@@ -20,6 +20,29 @@ constexpr int kTileThreads = 256;
 constexpr int kPerThread = kTileSyms / kTileThreads;
 // LDS slots for a tile's rule offsets: at most kTileSyms + 2 rules overlap a tile.
 constexpr int kTileRuleSlots = kTileSyms + 4;
+// Passes that keep per-block tables (histograms, bucket cursors) walk
+// kSubTiles consecutive tiles per workgroup: blocks of kBlockSyms symbols.
+constexpr int kSubTiles = 4;
+constexpr int kBlockSyms = kTileSyms * kSubTiles;
+// Word count by buckets of consecutive word ids: a bucket's counters
+// (kWcBucket x uint64) fit in LDS. Entries pack (weight << kWcBits | local id).
+constexpr int kWcBits = 12;
+constexpr int kWcBucket = 1 << kWcBits;
+constexpr int kWcMaxBuckets = 4096;  // vocabularies up to 2^24 words use buckets
+// In-degrees the same way: buckets of 4096 consecutive rule ids, one uint16
+// entry per rule reference (low 12 bits of the child id, bit 15 = the
+// reference sits in the root).
+constexpr int kRcBits = 12;
+constexpr int kRcBucket = 1 << kRcBits;
+constexpr int kRcMaxBuckets = 4096;  // grammars up to 2^24 rules
+constexpr uint16_t kRcRootFlag = 0x8000;
+// Per-block runs of a bucket are ordered XCD by XCD (workgroups are dispatched
+// to the 8 XCDs round-robin), so neighbouring runs are written through the
+// same L2. A table row holds nslot = 8 * ceil(nblk / 8) slots.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t xcd_slot(int64_t blk, int64_t nslot) {
+  return (blk % kXcds) * (nslot / kXcds) + blk / kXcds;
+}
 
 // Bits of the validation status word.
 enum : uint32_t {
@@ -42,6 +65,12 @@ struct DevGrammar {
   uint64_t* w;               // [R] top-down weights, w[0] = 1
   int32_t* level_rule;       // [R-1] rules grouped by level (level 1 first)
   int32_t* level_off;        // [D+2] level d occupies level_rule[level_off[d] .. level_off[d+1]), d >= 1
+  int64_t nblk;              // ceil(S / kBlockSyms)
+  int64_t nslot;             // kXcds * ceil(nblk / kXcds): slots per bucket row
+  int32_t wc_nb;             // word buckets (0: vocabulary too large, word count uses direct atomics)
+  uint32_t* wc_off;          // [wc_nb * nslot] bucket-major exclusive offsets of word entries
+  int32_t rc_nb;             // rule buckets for in-degrees (0: too many rules, direct atomics)
+  uint32_t* rc_off;          // [rc_nb * nslot] bucket-major exclusive offsets of reference entries
 };
 
 // Load-phase scalars written by the kernels and read back once.
@@ -53,6 +82,9 @@ struct LoadCounters {
   uint64_t tokens;       // T
   uint64_t word_syms;    // W
   uint64_t root_words;   // words directly in the root body
+  int64_t frontier0;     // rules of level 1
+  int64_t wc_entries;    // word entries counted into wc_off (= W)
+  int64_t rc_entries;    // reference entries counted into rc_off (= S - W)
 };
 
 // ---------------------------------------------------------------------------
@@ -67,11 +99,17 @@ hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int
 hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc,
                               hipStream_t s);
 hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s);
-hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, int device,
-                         hipStream_t s);
+// in-degrees and initial weights from the reference entries (after the offsets are scanned)
+hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entries, const int64_t* n, hipStream_t s);
+hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
+                         int device, hipStream_t s);
 
 // word count and sort
-hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);
+hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics
+hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint64_t* entries, int64_t W,
+                                     hipStream_t s);
+hipError_t launch_scan_offsets(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
+int64_t scan_scratch_entries(int64_t n);
 struct SortScratch {
   uint64_t* key[2];
   uint32_t* val[2];

@@ -11,13 +11,14 @@
 // Differences from the paper's design (same results): the rounds are not
 // relaunched from the host until a stop flag stays set. One cooperative
 // launch walks the levels with a grid barrier between them, and each level's
-// ready rules are compacted into a frontier list (wave ballot + one atomic per
-// wave), so a round touches only the rules of that level rather than scanning
-// every rule's mask. In-degrees count occurrences (a rule used twice by the
+// ready rules are compacted into a frontier list (gathered per workgroup in
+// LDS, one global atomic per workgroup and level), so a round touches only
+// the rules of that level rather than scanning every rule's mask. In-degrees count occurrences (a rule used twice by the
 // same parent waits for both), which gives the same levels and weights.
 #include <hip/hip_cooperative_groups.h>
 
 #include "device.h"
+#include "radix.h"
 
 namespace cg = cooperative_groups;
 
@@ -101,43 +102,59 @@ hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t*
   return hipGetLastError();
 }
 
-// Position-parallel scan of every body: symbol ranges, word totals, and the
-// in-edges of the top-down traversal. An occurrence of c in the root adds 1
-// to c's initial weight (its frequency in the root); an occurrence in any
-// other body adds 1 to c's count of pending in-edges.
+// Position-parallel scan of every body: symbol ranges and word totals, plus
+// two per-block histograms that fix where later passes place their entries:
+// word symbols per word bucket (wc_off) and rule references per rule bucket
+// (rc_off). Each workgroup walks kSubTiles tiles. Dynamic LDS: the tile's
+// rule offsets, then the two histograms.
 __global__ __launch_bounds__(kTileThreads) void k_scan_symbols(DevGrammar g, int32_t* pend, LoadCounters* lc) {
-  __shared__ int32_t roff[kTileRuleSlots];
-  const Tile t = tile_begin(g, blockIdx.x, roff);
-  const int32_t q0 = threadIdx.x * kPerThread;
-  int32_t v[kPerThread];
-  tile_load_syms(g, t, q0, v);
+  extern __shared__ int32_t lds_scan[];
+  int32_t* roff = lds_scan;
+  uint32_t* whist = reinterpret_cast<uint32_t*>(lds_scan + kTileRuleSlots);
+  uint32_t* rhist = whist + g.wc_nb;
+  const int wnb = g.wc_nb, rnb = g.rc_nb;
+  for (int b = threadIdx.x; b < wnb + rnb; b += blockDim.x) whist[b] = 0;
   uint32_t bad = 0;
   uint64_t words = 0, root_words = 0;
-  if (q0 < t.len) {
-    int32_t j = tile_find(roff, t.nr, q0);
-    int32_t next = roff[j + 1];
+  for (int sub = 0; sub < kSubTiles; ++sub) {
+    const int64_t tile = (int64_t)blockIdx.x * kSubTiles + sub;
+    if (tile >= g.ntiles) break;  // uniform for the block
+    const Tile t = tile_begin(g, tile, roff);
+    const int32_t q0 = threadIdx.x * kPerThread;
+    int32_t v[kPerThread];
+    tile_load_syms(g, t, q0, v);
+    if (q0 < t.len) {
+      int32_t j = tile_find(roff, t.nr, q0);
+      int32_t next = roff[j + 1];
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      const int32_t q = q0 + k;
-      if (q >= t.len) break;
-      while (q >= next) next = roff[++j + 1];
-      const int32_t r = t.r0 + j;
-      const int32_t s = v[k];
-      if (s >= 0) {
-        if (s >= g.V) {
-          bad |= ST_BAD_WORD;
+      for (int k = 0; k < kPerThread; ++k) {
+        const int32_t q = q0 + k;
+        if (q >= t.len) continue;
+        while (q >= next) next = roff[++j + 1];
+        const int32_t r = t.r0 + j;
+        const int32_t s = v[k];
+        if (s >= 0) {
+          if (s >= g.V) {
+            bad |= ST_BAD_WORD;
+          } else {
+            ++words;
+            root_words += (r == 0);
+            if (wnb) atomicAdd(&whist[s >> kWcBits], 1u);
+          }
         } else {
-          ++words;
-          root_words += (r == 0);
+          const int64_t c = -(int64_t)s;
+          if (c >= g.R) bad |= ST_BAD_REF;
+          else if (rnb) atomicAdd(&rhist[c >> kRcBits], 1u);
+          else if (r == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), 1ull);
+          else atomicAdd(&pend[c], 1);
         }
-      } else {
-        const int64_t c = -(int64_t)s;
-        if (c >= g.R) bad |= ST_BAD_REF;
-        else if (r == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), 1ull);
-        else atomicAdd(&pend[c], 1);
       }
     }
+    __syncthreads();  // roff is rewritten by the next tile
   }
+  const int64_t slot = xcd_slot(blockIdx.x, g.nslot);
+  for (int b = threadIdx.x; b < wnb; b += blockDim.x) g.wc_off[(int64_t)b * g.nslot + slot] = whist[b];
+  for (int b = threadIdx.x; b < rnb; b += blockDim.x) g.rc_off[(int64_t)b * g.nslot + slot] = rhist[b];
   words = wave_sum_u64(words);
   root_words = wave_sum_u64(root_words);
   if (lane_id() == 0) {
@@ -149,35 +166,243 @@ __global__ __launch_bounds__(kTileThreads) void k_scan_symbols(DevGrammar g, int
 
 hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s) {
   if (g.ntiles == 0) return hipSuccess;
-  k_scan_symbols<<<(unsigned)g.ntiles, kTileThreads, 0, s>>>(g, pend, lc);
+  const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.wc_nb + g.rc_nb);
+  k_scan_symbols<<<(unsigned)g.nblk, kTileThreads, shmem, s>>>(g, pend, lc);
   return hipGetLastError();
 }
 
-// Level 1: the rules with no pending in-edge (used only by the root, or not
-// at all). Also sets the root's weight to 1.
-__global__ void k_frontier0(DevGrammar g, const int32_t* pend, int32_t* level_cnt) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c == 0) g.w[0] = 1;
-  const bool ready = c >= 1 && c < g.R && pend[c] == 0;
-  const int32_t slot = wave_append(ready, &level_cnt[1]);
-  if (ready) g.level_rule[slot] = (int32_t)c;
+// In-degree scatter: one uint16 entry per rule reference into the bucket of
+// its child, at the block's cursor (offsets from the scan above).
+__global__ __launch_bounds__(kTileThreads) void k_ref_scatter(DevGrammar g, uint16_t* entries) {
+  extern __shared__ int32_t lds_ref[];
+  int32_t* roff = lds_ref;
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(lds_ref + kTileRuleSlots);
+  const int64_t slot = xcd_slot(blockIdx.x, g.nslot);
+  for (int b = threadIdx.x; b < g.rc_nb; b += blockDim.x) cursor[b] = g.rc_off[(int64_t)b * g.nslot + slot];
+  for (int sub = 0; sub < kSubTiles; ++sub) {
+    const int64_t tile = (int64_t)blockIdx.x * kSubTiles + sub;
+    if (tile >= g.ntiles) break;  // uniform for the block
+    const Tile t = tile_begin(g, tile, roff);
+    const int32_t q0 = threadIdx.x * kPerThread;
+    if (q0 < t.len) {
+      int32_t v[kPerThread];
+      tile_load_syms(g, t, q0, v);
+      int32_t j = tile_find(roff, t.nr, q0);
+      int32_t next = roff[j + 1];
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        const int32_t q = q0 + k;
+        if (q >= t.len) continue;
+        while (q >= next) next = roff[++j + 1];
+        const int32_t s = v[k];
+        const int64_t c64 = -(int64_t)s;
+        if (s < 0 && c64 < g.R) {  // out-of-range ids were not counted; the grammar is rejected
+          const uint32_t c = (uint32_t)c64;
+          const uint32_t at = atomicAdd(&cursor[c >> kRcBits], 1u);
+          entries[at] = (uint16_t)((c & (kRcBucket - 1)) | (t.r0 + j == 0 ? kRcRootFlag : 0));
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
-// The level walk (one cooperative launch). Level d is level_rule[lo, hi).
-// Every rule p of the level adds its (final) weight to each sub-rule
-// occurrence and retires one pending in-edge of it; a sub-rule whose last
-// in-edge retires joins level d+1, appended after hi. Counts of level d+1
-// go to level_cnt[d+1], so they are stable once the grid barrier has passed.
-// The same walk sums weight x (words in body) over the non-root rules, the
-// number of words they contribute to the text.
-__global__ __launch_bounds__(256) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc) {
+// In-degree reduce over fixed chunks of the entry array (bucket sizes are
+// very uneven: preorder numbering gives the most used rules small ids).
+// Occurrences in the root add to the initial weight (frequency in the root),
+// the others to the count of pending in-edges; per bucket segment both are
+// summed in LDS and added to the zeroed outputs with coalesced atomics. The
+// most common key of each wave step is merged with one ballot first (every
+// entry counts 1), which takes the bulk of the same-address LDS updates.
+constexpr int kRcThreads = 1024;
+constexpr int64_t kRcChunk = 32 * kRcThreads;
+
+__global__ __launch_bounds__(kRcThreads) void k_ref_reduce(DevGrammar g, const uint16_t* entries, const int64_t* total,
+                                                           int32_t* pend) {
+  __shared__ uint32_t in_root[kRcBucket];
+  __shared__ uint32_t in_rules[kRcBucket];
+  __shared__ int first_bucket;
+  const int64_t n = *total;
+  const int64_t c_lo = (int64_t)blockIdx.x * kRcChunk;
+  if (c_lo >= n) return;  // uniform for the block
+  const int64_t c_hi = c_lo + kRcChunk < n ? c_lo + kRcChunk : n;
+  for (int i = threadIdx.x; i < kRcBucket; i += blockDim.x) in_root[i] = 0, in_rules[i] = 0;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = g.rc_nb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)g.rc_off[(int64_t)mid * g.nslot] <= c_lo) lo = mid;
+      else hi = mid - 1;
+    }
+    first_bucket = lo;
+  }
+  __syncthreads();
+  for (int b = first_bucket; b < g.rc_nb; ++b) {
+    const int64_t b_lo = g.rc_off[(int64_t)b * g.nslot];
+    const int64_t b_hi = (b + 1 < g.rc_nb) ? (int64_t)g.rc_off[(int64_t)(b + 1) * g.nslot] : n;
+    if (b_lo >= c_hi) break;
+    const int64_t lo = b_lo > c_lo ? b_lo : c_lo, hi = b_hi < c_hi ? b_hi : c_hi;
+    for (int64_t i0 = lo; i0 < hi; i0 += blockDim.x) {  // uniform trip count: whole waves step together
+      const int64_t i = i0 + threadIdx.x;
+      const bool valid = i < hi;
+      const uint32_t key = valid ? entries[i] : 0xffffffffu;
+      const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);
+      const uint64_t same = __ballot(valid && key == key0);
+      uint32_t add = 1;
+      if (key == key0) add = (lane_id() == __ffsll((unsigned long long)same) - 1) ? (uint32_t)__popcll(same) : 0u;
+      if (valid && add)
+        atomicAdd((key & kRcRootFlag) ? &in_root[key & (kRcBucket - 1)] : &in_rules[key & (kRcBucket - 1)], add);
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)b * kRcBucket;
+    for (int i = threadIdx.x; i < kRcBucket; i += blockDim.x) {
+      const int64_t c = base + i;
+      const uint32_t r = in_root[i], p = in_rules[i];
+      in_root[i] = 0, in_rules[i] = 0;
+      if (c >= g.R) continue;
+      if (r) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)r);
+      if (p) atomicAdd(&pend[c], (int32_t)p);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entries, const int64_t* n, hipStream_t s) {
+  if (g.rc_nb == 0) return hipSuccess;  // counted with direct atomics by the scan
+  hipError_t e0 = launch_fill_u64(g.w, g.R, 0, s);
+  if (e0 == hipSuccess) e0 = launch_fill_i32(pend, g.R, 0, s);
+  if (e0 != hipSuccess) return e0;
+  if (g.ntiles > 0) {
+    const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.rc_nb);
+    k_ref_scatter<<<(unsigned)g.nblk, kTileThreads, shmem, s>>>(g, entries);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // at most S entries; chunks past the actual count exit at once
+  const int64_t chunks = (g.S + kRcChunk - 1) / kRcChunk;
+  if (chunks > 0) {
+    k_ref_reduce<<<(unsigned)chunks, kRcThreads, 0, s>>>(g, entries, n, pend);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  k_fill_u64<<<1, 64, 0, s>>>(g.w, 1, 1);  // the root's weight
+  return hipGetLastError();
+}
+
+// Level 1 = the rules with no pending in-edge (used only by the root, or not
+// at all), compacted in rule-id order: a count per block of kBlockSyms rules,
+// an exclusive scan, then every block writes its rules at its offset.
+__global__ __launch_bounds__(256) void k_zero_count(const int32_t* pend, int64_t R, uint32_t* cnt) {
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t r = i0 + k;
+    if (r >= 1 && r < R && pend[r] == 0) ++c;
+  }
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  block_exclusive_scan_256(c, lds, &total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_zero_write(const int32_t* pend, int64_t R, const uint32_t* off,
+                                                    int32_t* out) {
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+  bool z[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t r = i0 + k;
+    z[k] = r >= 1 && r < R && pend[r] == 0;
+    c += z[k];
+  }
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (z[k]) out[pos++] = (int32_t)(i0 + k);
+}
+
+// The level walk (one cooperative launch, one 1024-thread workgroup per CU).
+// Level d is level_rule[lo, hi). Every rule p of the level adds its (final)
+// weight to each sub-rule occurrence and retires one pending in-edge of it;
+// a sub-rule whose last in-edge retires joins level d+1.
+//  - Contributions to the same sub-rule are first merged per workgroup in an
+//    LDS hash table (sub-rule -> weight sum, edge count) and applied with one
+//    pair of global atomics per table entry at the end of the level, so a
+//    sub-rule used by thousands of parents does not serialize thousands of
+//    atomics on one address. When the probe sequence is full the occurrence
+//    goes straight to global memory.
+//  - New members of level d+1 are gathered per workgroup in LDS and appended
+//    with one global atomic per workgroup, after hi; the count of level d+1
+//    lives in level_cnt[d+1] and is stable once the grid barrier has passed.
+// The same walk sums weight x (words in body) over the non-root rules.
+constexpr int kLevelThreads = 1024;
+constexpr int kLevelList = 8192;
+constexpr int kAggBits = 12;
+constexpr int kAggSlots = 1 << kAggBits;
+constexpr int kAggProbes = 8;
+
+struct LevelLds {
+  int32_t list[kLevelList];
+  int32_t key[kAggSlots];
+  uint64_t wsum[kAggSlots];
+  uint32_t cnt[kAggSlots];
+  int32_t list_n, list_base;
+  uint64_t part[kLevelThreads / 64];
+};
+
+// Append c (where `ready`) to the workgroup's list of level d+1; lanes past
+// the LDS capacity append directly to the global level list.
+__device__ __forceinline__ void level_append(bool ready, int32_t c, LevelLds& L, DevGrammar& g, int32_t* level_cnt,
+                                             int32_t d, int32_t hi) {
+  const uint64_t mask = __ballot(ready);
+  if (!mask) return;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  const int32_t n = (int32_t)__popcll(mask);
+  int32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&L.list_n, n);
+  base = __shfl(base, leader);
+  const int32_t at = base + (int32_t)__popcll(mask & lanes_below());
+  const bool spill = ready && at >= kLevelList;
+  if (ready && !spill) L.list[at] = c;
+  if (base + n > kLevelList) {
+    const int32_t slot = wave_append(spill, &level_cnt[d + 1]);
+    if (spill) g.level_rule[hi + slot] = c;
+  }
+}
+
+__device__ __forceinline__ bool agg_add(LevelLds& L, int32_t c, uint64_t w) {
+  const uint32_t h = ((uint32_t)c * 2654435761u) >> (32 - kAggBits);
+#pragma unroll
+  for (int p = 0; p < kAggProbes; ++p) {
+    const uint32_t slot = (h + p) & (kAggSlots - 1);
+    int32_t k = __hip_atomic_load(&L.key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == -1) k = atomicCAS(&L.key[slot], -1, c);
+    if (k == -1 || k == c) {
+      if (w) atomicAdd(reinterpret_cast<unsigned long long*>(&L.wsum[slot]), (unsigned long long)w);
+      atomicAdd(&L.cnt[slot], 1u);
+      return true;
+    }
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt,
+                                                          LoadCounters* lc) {
   cg::grid_group grid = cg::this_grid();
+  __shared__ LevelLds L;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   int32_t lo = 0;
-  int32_t hi = __hip_atomic_load(&level_cnt[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int32_t hi = (int32_t)__hip_atomic_load(&lc->frontier0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int32_t d = 1;
   uint64_t tokens = 0;
+  for (int i = threadIdx.x; i < kAggSlots; i += blockDim.x) L.key[i] = -1, L.wsum[i] = 0, L.cnt[i] = 0;
+  if (threadIdx.x == 0) L.list_n = 0;
+  __syncthreads();
   while (lo < hi) {
     for (int64_t i = lo + tid; i < hi; i += nthreads) {
       const int32_t p = g.level_rule[i];
@@ -192,16 +417,38 @@ __global__ __launch_bounds__(256) void k_levels(DevGrammar g, int32_t* pend, int
           ++words;
         } else {
           c = -s;
-          if (c < g.R) {  // out-of-range ids are reported by the scan; never touched here
+          // out-of-range ids are reported by the scan and never touched here
+          if (c < g.R && !agg_add(L, c, wp)) {
             if (wp) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)wp);
             ready = atomicSub(&pend[c], 1) == 1;
           }
         }
-        const int32_t slot = wave_append(ready, &level_cnt[d + 1]);
-        if (ready) g.level_rule[hi + slot] = c;
+        level_append(ready, c, L, g, level_cnt, d, hi);
       }
       tokens += wp * words;
     }
+    __syncthreads();
+    // apply the merged contributions
+    for (int slot = threadIdx.x; slot < kAggSlots; slot += blockDim.x) {
+      const int32_t c = L.key[slot];
+      bool ready = false;
+      if (c >= 0) {
+        const uint64_t dw = L.wsum[slot];
+        const int32_t dn = (int32_t)L.cnt[slot];
+        if (dw) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)dw);
+        ready = atomicSub(&pend[c], dn) == dn;
+        L.key[slot] = -1;
+        L.wsum[slot] = 0;
+        L.cnt[slot] = 0;
+      }
+      level_append(ready, c, L, g, level_cnt, d, hi);
+    }
+    __syncthreads();
+    const int32_t n_local = L.list_n < kLevelList ? L.list_n : kLevelList;
+    if (threadIdx.x == 0) L.list_base = n_local ? atomicAdd(&level_cnt[d + 1], n_local) : 0;
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < n_local; k += blockDim.x) g.level_rule[hi + L.list_base + k] = L.list[k];
+    if (threadIdx.x == 0) L.list_n = 0;
     grid.sync();
     const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) {
@@ -213,12 +460,12 @@ __global__ __launch_bounds__(256) void k_levels(DevGrammar g, int32_t* pend, int
     ++d;
   }
   // block sum of the token contributions, one atomic per block
-  __shared__ uint64_t part[4];
   tokens = wave_sum_u64(tokens);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = tokens;
+  if (lane_id() == 0) L.part[threadIdx.x >> 6] = tokens;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint64_t sum = part[0] + part[1] + part[2] + part[3];
+    uint64_t sum = 0;
+    for (int w = 0; w < kLevelThreads / 64; ++w) sum += L.part[w];
     if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&lc->tokens), (unsigned long long)sum);
   }
   if (tid == 0) {
@@ -227,23 +474,37 @@ __global__ __launch_bounds__(256) void k_levels(DevGrammar g, int32_t* pend, int
   }
 }
 
-hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, int device,
-                         hipStream_t s) {
-  k_frontier0<<<(unsigned)((g.R + 255) / 256), 256, 0, s>>>(g, pend, level_cnt);
+hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
+                         int device, hipStream_t s) {
+  // level 1 by compaction (scratch: per-block counts, then the scan's block sums)
+  const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
+  k_zero_count<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  e = launch_scan_u32(scratch, nb, &lc->frontier0, scratch + nb, s);
+  if (e != hipSuccess) return e;
+  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch, g.level_rule);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   int per_cu = 0, cus = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), 256, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), kLevelThreads, 0);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  int64_t want = (g.R + 255) / 256;
-  int64_t cap = (int64_t)per_cu * cus;
-  if (cap > 4 * (int64_t)cus) cap = 4 * (int64_t)cus;  // enough waves for the widest level
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int64_t want = (g.R + kLevelThreads - 1) / kLevelThreads;
+  const int64_t cap = cus;  // one workgroup per CU: few participants in every grid barrier
   const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
   DevGrammar gg = g;
   void* args[] = {&gg, &pend, &level_cnt, &lc};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(256), args, 0, s);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(kLevelThreads), args, 0,
+                                    s);
 }
+
+// Scan of the word-bucket offsets (bucket-major), for the host.
+hipError_t launch_scan_offsets(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s) {
+  return launch_scan_u32(a, n, total, sums, s);
+}
+int64_t scan_scratch_entries(int64_t n) { return scan_sums_entries(n); }
 
 }  // namespace gt

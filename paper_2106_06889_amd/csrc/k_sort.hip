@@ -48,10 +48,7 @@ __global__ __launch_bounds__(256) void k_nz_write(const uint64_t* counts, int32_
     }
 }
 
-int64_t sort_scratch_hist_entries(int64_t n) {
-  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
-  return 256 * (nb > 0 ? nb : 1) + 1;
-}
+int64_t sort_scratch_hist_entries(int64_t n) { return radix_hist_entries(n); }
 
 hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,
                                 uint64_t* cnt_out, int64_t* num_out, hipStream_t s) {
@@ -60,7 +57,7 @@ hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes
   k_nz_count<<<nb, 256, 0, s>>>(counts, V, blk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_scan_u32(blk, nb, sc.num, s);  // exclusive offsets; total K -> *sc.num
+  e = launch_scan_u32(blk, nb, sc.num, blk + nb, s);  // exclusive offsets; total K -> *sc.num
   if (e != hipSuccess) return e;
   k_nz_write<<<nb, 256, 0, s>>>(counts, V, blk, sc.key[0], sc.val[0]);
   e = hipGetLastError();

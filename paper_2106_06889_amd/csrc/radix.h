@@ -35,7 +35,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 
 // Exclusive scan of a[0..n) in place by one 1024-thread block; the total goes
 // to *total (int64) if non-null.
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int64_t n, int64_t* total) {
+static __global__ __attribute__((unused)) __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int64_t n, int64_t* total) {
   __shared__ uint64_t wsum[16];
   const int64_t per = (n + 1023) / 1024;
   const int64_t lo = threadIdx.x * per;
@@ -66,8 +66,55 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int64_t n, int64
   if (threadIdx.x == 0 && total) *total = (int64_t)tot;
 }
 
-inline hipError_t launch_scan_u32(uint32_t* a, int64_t n, int64_t* total, hipStream_t s) {
-  k_scan_u32<<<1, 1024, 0, s>>>(a, n, total);
+// Multi-block exclusive scan of u32 values (sums must fit 32 bits): block
+// sums of 4096-element chunks, one small scan of those, then every chunk
+// scanned in place with its offset. `sums` needs scan_sums_entries(n).
+inline int64_t scan_sums_entries(int64_t n) { return (n + kRadixTile - 1) / kRadixTile + 1; }
+
+static __global__ __attribute__((unused)) __launch_bounds__(256) void k_scan_sums(const uint32_t* a, int64_t n, uint32_t* sums) {
+  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) c += a[i0 + k];
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  block_exclusive_scan_256(c, lds, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+static __global__ __attribute__((unused)) __launch_bounds__(256) void k_scan_apply(uint32_t* a, int64_t n, const uint32_t* sums) {
+  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
+  uint32_t v[16], c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = (i0 + k < n) ? a[i0 + k] : 0u;
+    c += v[k];
+  }
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  uint32_t run = sums[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) {
+      a[i0 + k] = run;
+      run += v[k];
+    }
+}
+
+inline hipError_t launch_scan_u32(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s) {
+  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+  if (nb <= 1) {
+    k_scan_u32<<<1, 1024, 0, s>>>(a, n, total);
+    return hipGetLastError();
+  }
+  k_scan_sums<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_u32<<<1, 1024, 0, s>>>(sums, nb, total);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_apply<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
   return hipGetLastError();
 }
 
@@ -77,7 +124,7 @@ __device__ __forceinline__ uint32_t radix_digit(uint64_t k, int shift, bool desc
 
 // Digit histogram of every tile: hist[d * nb + b] (digit-major, so that one
 // exclusive scan gives every tile's output offset per digit).
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t* key, const int64_t* num, int shift, bool desc,
+static __global__ __attribute__((unused)) __launch_bounds__(256) void k_radix_hist(const uint64_t* key, const int64_t* num, int shift, bool desc,
                                                     uint32_t* hist, int nb) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -161,8 +208,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* kin, cons
 // Sort (key, val) pairs by the bits [bit_lo, bit_hi) of the key (ascending,
 // or descending with desc), stably. n = *num (device) <= cap. The input is
 // (k0, v0); (k1, v1) is scratch of the same size; the result lands in
-// (kout, vout). hist needs sort_hist_entries(cap) entries. bit_hi - bit_lo
+// (kout, vout). hist needs radix_hist_entries(cap) entries. bit_hi - bit_lo
 // is rounded up to whole bytes.
+inline int64_t radix_hist_entries(int64_t cap) {
+  const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
+  return 256 * (nb > 0 ? nb : 1) + scan_sums_entries(256 * (nb > 0 ? nb : 1));
+}
+
 template <typename V>
 hipError_t radix_sort_pairs(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int64_t* num, int64_t cap, int bit_lo,
                             int bit_hi, bool desc, uint32_t* hist, uint64_t* kout, V* vout, hipStream_t s) {
@@ -178,7 +230,7 @@ hipError_t radix_sort_pairs(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int6
     k_radix_hist<<<nb, 256, 0, s>>>(ksrc, num, shift, desc, hist, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_scan_u32(hist, (int64_t)256 * nb, nullptr, s);
+    e = launch_scan_u32(hist, (int64_t)256 * nb, nullptr, hist + (int64_t)256 * nb, s);
     if (e != hipSuccess) return e;
     k_radix_scatter<V><<<nb, 256, 0, s>>>(ksrc, vsrc, kdst, vdst, num, shift, desc, hist, nb);
     e = hipGetLastError();

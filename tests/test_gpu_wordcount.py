@@ -146,3 +146,12 @@ def test_device_and_borrowed_inputs(ctx):
         G = ctx.load(*dev, g.vocab, borrow=borrow)
         assert np.array_equal(gt.to_u64(G.word_count()), want)
         G.free()
+
+
+def test_vocabulary_beyond_bucket_table(ctx):
+    """Vocabularies above 2^24 words take the direct-atomic word count path."""
+    V = (1 << 24) + 5
+    rng = np.random.default_rng(3)
+    tok = rng.choice(np.array([0, 7, V - 1, 1 << 20, (1 << 24) + 1], np.int64), size=3000).astype(np.int32)
+    g = synth.compress(tok, np.array([0, 1000, 3000], np.int64), V)
+    check_wc_sort(ctx, g, expect_tokens=3000)
