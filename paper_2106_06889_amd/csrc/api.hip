@@ -112,6 +112,10 @@ struct gtadoc_grammar_s {
   gt::DevGrammar d{};
   gtadoc_stats st{};
   std::vector<int32_t> level_off;  // host copy, level_off[d] for d = 1..D+1
+  // head/tail/len buffers for sequences (first use of sequence count)
+  uint64_t* seq_len = nullptr;
+  int32_t* seq_head = nullptr;
+  int32_t* seq_tail = nullptr;
 };
 
 struct gtadoc_result_s {
@@ -461,11 +465,114 @@ int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
   return fail(GTADOC_ERR_UNSUPPORTED, "inverted index: not available in this build");
 }
 
+namespace {
+
+// Byte mask of the packed n-gram keys: word ids < V occupy bitlen(V-1) bits
+// at bit 0 and 32 (n = 2) or at bits 0, 21 and 42 (n = 3).
+uint64_t gram_byte_mask(int n, int32_t V) {
+  const int b = std::max(1, bitlen((uint64_t)(V - 1)));
+  uint64_t mask = 0;
+  auto cover = [&](int lo, int hi) {
+    for (int x = lo / 8; x * 8 < hi && x < 8; ++x) mask |= 1ull << x;
+  };
+  if (n == 2) {
+    cover(0, b);
+    cover(32, 32 + b);
+  } else {
+    cover(0, b);
+    cover(21, 21 + b);
+    cover(42, 42 + b);
+  }
+  return mask;
+}
+
+gtadoc_result new_result(gtadoc_ctx ctx) {
+  auto* r = new (std::nothrow) gtadoc_result_s;
+  if (r) r->ctx = ctx;
+  return r;
+}
+
+}  // namespace
+
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
-  (void)stream;
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   if (n < 2 || n > 3) return fail(GTADOC_ERR_INVALID_ARG, "n must be 2 or 3");
-  return fail(GTADOC_ERR_UNSUPPORTED, "sequence count: not available in this build");
+  const gt::DevGrammar& d = g->d;
+  if (n == 3 && d.V > (1 << 21)) return fail(GTADOC_ERR_UNSUPPORTED, "trigram keys need vocab <= 2^21");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  const int64_t R = d.R, S = d.S;
+  // initialization phase: head/tail/len buffers, children first (kept with the grammar)
+  if (!g->seq_len) {
+    std::vector<Block> kept;
+    auto* len = call.keep<uint64_t>(R, kept);
+    auto* head = call.keep<int32_t>(2 * R, kept);
+    auto* tail = call.keep<int32_t>(2 * R, kept);
+    if (!len || !head || !tail) {
+      release_all(g->ctx, kept);
+      return oom("head/tail buffers", 24ull * R);
+    }
+    hipError_t e = gt::launch_headtail(d, g->level_off.data(), (int32_t)g->st.depth, len, head, tail, s);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      release_all(g->ctx, kept);
+      return fail(GTADOC_ERR_HIP, "head/tail: %s", hipGetErrorString(e));
+    }
+    g->blocks.insert(g->blocks.end(), kept.begin(), kept.end());
+    g->seq_len = len, g->seq_head = head, g->seq_tail = tail;
+  }
+  // graph traversal phase: owned windows into an exact table sized from the
+  // per-rule bound (at most n-1 windows start at every body position)
+  const uint64_t bound = (uint64_t)(n - 1) * (uint64_t)S + 1;
+  uint64_t cap = 1024;
+  while (cap < 2 * bound) cap <<= 1;
+  auto* keys = call.scratch<uint64_t>((int64_t)cap);
+  auto* vals = call.scratch<uint64_t>((int64_t)cap);
+  const int64_t nb = ((int64_t)cap + 4095) / 4096;
+  auto* cnt = call.scratch<uint32_t>(nb + gt::scan_scratch_entries(nb));
+  auto* flags = call.scratch<int64_t>(2);  // [0] distinct keys, [1] overflow flag
+  if (!keys || !vals || !cnt || !flags) return oom("sequence table", 16 * cap);
+  HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(flags), 4, 0, s));
+  HIP_TRY(gt::launch_seq_windows(d, n, g->seq_len, g->seq_head, g->seq_tail, keys, vals, cap,
+                                 reinterpret_cast<uint32_t*>(flags + 1), s));
+  HIP_TRY(gt::launch_occ_count(keys, (int64_t)cap, cnt, flags, cnt + nb, s));
+  auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
+  HIP_TRY(hipMemcpyAsync(pc, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (pc[1] & 0xffffffff) return fail(GTADOC_ERR_OVERFLOW, "sequence table full");
+  const int64_t U = pc[0];
+  gtadoc_result res = new_result(g->ctx);
+  if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  auto* okey = call.keep<uint64_t>(U, res->blocks);
+  auto* oval = call.keep<uint64_t>(U, res->blocks);
+  auto* k0 = call.scratch<uint64_t>(U);
+  auto* v0 = call.scratch<uint64_t>(U);
+  auto* k1 = call.scratch<uint64_t>(U);
+  auto* v1 = call.scratch<uint64_t>(U);
+  auto* hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(U));
+  if (!okey || !oval || !k0 || !v0 || !k1 || !v1 || !hist) {
+    release_all(g->ctx, res->blocks);
+    delete res;
+    return oom("sequence result", 48 * (uint64_t)U);
+  }
+  if (U > 0) {
+    hipError_t e = gt::launch_occ_write(keys, vals, (int64_t)cap, cnt, k0, v0, s);
+    if (e == hipSuccess)
+      e = gt::launch_sort_keys_u64(k0, v0, k1, v1, flags, U, gram_byte_mask(n, d.V), hist, okey, oval, s);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      release_all(g->ctx, res->blocks);
+      delete res;
+      return fail(GTADOC_ERR_HIP, "sequence sort: %s", hipGetErrorString(e));
+    }
+  }
+  res->a[0] = {okey, U, 8};
+  res->a[1] = {oval, U, 8};
+  res->na = 2;
+  *out = res;
+  return GTADOC_OK;
 }
 
 int gtadoc_result_array(gtadoc_result res, int index, void** dptr, int64_t* length, int* elem_bytes) {

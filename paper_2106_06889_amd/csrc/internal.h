@@ -118,6 +118,19 @@ struct SortScratch {
   int64_t capacity;
 };
 int64_t sort_scratch_hist_entries(int64_t n);
+
+// sequence count
+hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
+                           int32_t* head, int32_t* tail, hipStream_t s);
+hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
+                              const int32_t* tail, uint64_t* keys, uint64_t* vals, uint64_t cap, uint32_t* overflow,
+                              hipStream_t s);
+hipError_t launch_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
+                            hipStream_t s);
+hipError_t launch_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap, const uint32_t* off,
+                            uint64_t* okey, uint64_t* oval, hipStream_t s);
+hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
+                                uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s);
 hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,
                                 uint64_t* cnt_out, int64_t* num_out, hipStream_t s);
 

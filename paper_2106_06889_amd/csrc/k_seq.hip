@@ -1,0 +1,297 @@
+// k_seq.hip -- sequence count: occurrences of every run of n consecutive
+// words (n = 2, 3) inside one file, without decompressing.
+//
+// Paper: Section "Data Structures", head and tail structures (each rule keeps
+// the first and last words of its expansion so that its parents can count
+// the sequences that cross into it); Section "Sequence Support"
+// (initialization phase fills head and tail buffers children first; graph
+// traversal phase counts every rule's sequences into a shared hash table;
+// the memory bound of the per-rule table, Eq. "upperLimit").
+//
+// Every length-n window of a file lies inside the expansion of exactly one
+// deepest rule occurrence; that rule "owns" it. A rule's owned windows are
+// the windows of its body that are not inside one child's expansion, and a
+// window counts weight(rule) times. Here they are enumerated position by
+// position: the piece at body position q (a word, or a child's expansion)
+// starts the windows whose first word is among its last n-1 words and that
+// run past its end; their remaining words come from the heads of the next
+// pieces. Per rule this gives wordSize + (n-1) x subRuleSize - (n-1)
+// windows whenever every child expands to at least n-1 words.
+//
+// Differences from the paper's design: head/tail buffers are filled level by
+// level from the deepest level (one launch per level) instead of a host loop
+// that retries rules whose children are not ready; the shared table is
+// lock-free open addressing (64-bit CAS on the key, 64-bit atomic add on the
+// count) instead of per-entry locks with relaunch on contention; the result
+// is compacted and radix-sorted by key.
+#include "device.h"
+#include "radix.h"
+
+namespace gt {
+
+constexpr uint64_t kEmptyKey = ~0ull;  // never a valid packed n-gram
+
+// head[2r..2r+1] = first min(len, 2) words of exp(r), tail[2r..2r+1] = last
+// min(len, 2) words in text order; len[r] = words in exp(r). Rules of one
+// level; their children (deeper levels) are done.
+__global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
+                                 int32_t* tail) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = rules[i];
+  const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  uint64_t L = 0;
+  int32_t h0 = -1, h1 = -1;
+  int hc = 0;
+  for (int64_t q = a; q < b; ++q) {
+    const int32_t s = g.sym[q];
+    if (s >= 0) {
+      ++L;
+      if (hc == 0) h0 = s, hc = 1;
+      else if (hc == 1) h1 = s, hc = 2;
+    } else {
+      const int32_t c = -s;
+      const uint64_t lc = len[c];
+      L += lc;
+      const int take = lc < 2 ? (int)lc : 2;
+      for (int j = 0; j < take && hc < 2; ++j) {
+        const int32_t x = head[2 * (int64_t)c + j];
+        if (hc == 0) h0 = x, hc = 1;
+        else h1 = x, hc = 2;
+      }
+    }
+  }
+  int32_t t_last = -1, t_prev = -1;  // collected from the right
+  int tc = 0;
+  for (int64_t q = b - 1; q >= a && tc < 2; --q) {
+    const int32_t s = g.sym[q];
+    if (s >= 0) {
+      if (tc == 0) t_last = s, tc = 1;
+      else t_prev = s, tc = 2;
+    } else {
+      const int32_t c = -s;
+      const uint64_t lc = len[c];
+      const int take = lc < 2 ? (int)lc : 2;
+      for (int j = take - 1; j >= 0 && tc < 2; --j) {
+        const int32_t x = tail[2 * (int64_t)c + j];
+        if (tc == 0) t_last = x, tc = 1;
+        else t_prev = x, tc = 2;
+      }
+    }
+  }
+  len[r] = L;
+  head[2 * (int64_t)r] = h0;
+  head[2 * (int64_t)r + 1] = h1;
+  if (L >= 2) {
+    tail[2 * (int64_t)r] = t_prev;
+    tail[2 * (int64_t)r + 1] = t_last;
+  } else {
+    tail[2 * (int64_t)r] = t_last;
+    tail[2 * (int64_t)r + 1] = -1;
+  }
+}
+
+hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
+                           int32_t* head, int32_t* tail, hipStream_t s) {
+  for (int32_t d = depth; d >= 1; --d) {
+    const int32_t lo = level_off_host[d], hi = level_off_host[d + 1];
+    if (hi <= lo) continue;
+    k_headtail_level<<<(unsigned)((hi - lo + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, hi - lo, len, head, tail);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdULL;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ULL;
+  x ^= x >> 33;
+  return x;
+}
+
+// Lock-free insert-or-add: the first thread to CAS an empty slot owns it for
+// that key; every occurrence then adds its weight to the slot's count.
+__device__ __forceinline__ void table_add(uint64_t* keys, uint64_t* vals, uint64_t mask, uint64_t key, uint64_t w,
+                                          uint32_t* overflow) {
+  uint64_t h = mix64(key) & mask;
+  for (uint64_t p = 0; p <= mask; ++p) {
+    uint64_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k == kEmptyKey) {
+      k = atomicCAS(reinterpret_cast<unsigned long long*>(&keys[h]), (unsigned long long)kEmptyKey,
+                    (unsigned long long)key);
+      if (k == kEmptyKey) k = key;
+    }
+    if (k == key) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&vals[h]), (unsigned long long)w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+  atomicOr(overflow, 1u);
+}
+
+__device__ __forceinline__ uint64_t pack_gram(const int32_t* x, int n) {
+  if (n == 2) return (uint64_t)(uint32_t)x[0] << 32 | (uint32_t)x[1];
+  return (uint64_t)(uint32_t)x[0] << 42 | (uint64_t)(uint32_t)x[1] << 21 | (uint32_t)x[2];
+}
+
+// Words of the piece at body position q: a word, or the first (head) / last
+// (tail) min(len, 2) words of a child's expansion.
+struct Piece {
+  int32_t w[2];
+  int cnt;
+};
+
+__device__ __forceinline__ Piece piece_head(const DevGrammar& g, const uint64_t* len, const int32_t* head, int32_t s) {
+  Piece p;
+  if (s >= 0) {
+    p.w[0] = s, p.cnt = 1;
+  } else {
+    const int64_t c = -(int64_t)s;
+    const uint64_t lc = len[c];
+    p.cnt = lc < 2 ? (int)lc : 2;
+    p.w[0] = head[2 * c];
+    p.w[1] = head[2 * c + 1];
+  }
+  return p;
+}
+
+__device__ __forceinline__ Piece piece_tail(const DevGrammar& g, const uint64_t* len, const int32_t* tail, int32_t s) {
+  Piece p;
+  if (s >= 0) {
+    p.w[0] = s, p.cnt = 1;
+  } else {
+    const int64_t c = -(int64_t)s;
+    const uint64_t lc = len[c];
+    p.cnt = lc < 2 ? (int)lc : 2;
+    p.w[0] = tail[2 * c];
+    p.w[1] = tail[2 * c + 1];
+  }
+  return p;
+}
+
+// Owned windows, position-parallel over the tiles of all bodies. The root is
+// split at file boundaries: windows never cross files.
+__global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int n, const uint64_t* len,
+                                                              const int32_t* head, const int32_t* tail, uint64_t* keys,
+                                                              uint64_t* vals, uint64_t mask, uint32_t* overflow) {
+  __shared__ int32_t roff[kTileRuleSlots];
+  const Tile t = tile_begin(g, blockIdx.x, roff);
+  const int32_t q0 = threadIdx.x * kPerThread;
+  if (q0 >= t.len) return;
+  int32_t j = tile_find(roff, t.nr, q0);
+  int32_t next = roff[j + 1];
+  int64_t f = -1, f_end = 0;  // file span of the current root position
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t qt = q0 + k;
+    if (qt >= t.len) break;
+    while (qt >= next) next = roff[++j + 1];
+    const int32_t r = t.r0 + j;
+    const int64_t q = t.a + qt;
+    int64_t end;
+    uint64_t wt;
+    if (r == 0) {
+      if (q >= f_end) {  // locate the file span holding q (binary search on file_off)
+        int64_t lo = 0, hi = g.F - 1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) >> 1;
+          if (g.file_off[mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        // skip empty spans that start at q
+        f = lo;
+        f_end = g.file_off[f + 1];
+      }
+      end = f_end;
+      wt = 1;
+    } else {
+      end = g.rule_off[r + 1];
+      wt = g.w[r];
+    }
+    if (wt == 0) continue;
+    const Piece st = piece_tail(g, len, tail, g.sym[q]);
+    const int starts = st.cnt < n - 1 ? st.cnt : n - 1;
+    // words after the piece: heads of the next pieces, at most n-1 of them
+    int32_t ahead[2];
+    int na = 0;
+    for (int64_t q2 = q + 1; q2 < end && na < n - 1; ++q2) {
+      const Piece p = piece_head(g, len, head, g.sym[q2]);
+      for (int x = 0; x < p.cnt && na < n - 1; ++x) ahead[na++] = p.w[x];
+    }
+    for (int s0 = st.cnt - starts; s0 < st.cnt; ++s0) {
+      int32_t win[3];
+      int wn = 0;
+      for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
+      for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];
+      if (wn == n) table_add(keys, vals, mask, pack_gram(win, n), wt, overflow);
+    }
+  }
+}
+
+hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
+                              const int32_t* tail, uint64_t* keys, uint64_t* vals, uint64_t cap, uint32_t* overflow,
+                              hipStream_t s) {
+  hipError_t e = launch_fill_u64(keys, (int64_t)cap, kEmptyKey, s);
+  if (e == hipSuccess) e = launch_fill_u64(vals, (int64_t)cap, 0, s);
+  if (e != hipSuccess || g.ntiles == 0) return e;
+  k_seq_windows<<<(unsigned)g.ntiles, kTileThreads, 0, s>>>(g, n, len, head, tail, keys, vals, cap - 1, overflow);
+  return hipGetLastError();
+}
+
+// Compaction of the occupied slots (slot order), then the caller sorts.
+__global__ __launch_bounds__(256) void k_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt) {
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) ++c;
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  block_exclusive_scan_256(c, lds, &total);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap,
+                                                   const uint32_t* off, uint64_t* okey, uint64_t* oval) {
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) ++c;
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) {
+      okey[pos] = keys[i0 + k];
+      oval[pos] = vals[i0 + k];
+      ++pos;
+    }
+}
+
+hipError_t launch_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
+                            hipStream_t s) {
+  const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
+  k_occ_count<<<(unsigned)nb, 256, 0, s>>>(keys, cap, cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scan_u32(cnt, nb, total, sums, s);
+}
+
+hipError_t launch_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap, const uint32_t* off,
+                            uint64_t* okey, uint64_t* oval, hipStream_t s) {
+  const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
+  k_occ_write<<<(unsigned)nb, 256, 0, s>>>(keys, vals, cap, off, okey, oval);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
+                                uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s) {
+  return radix_sort_pairs_bytes<uint64_t>(k0, v0, k1, v1, num, cap, byte_mask, false, hist, kout, vout, s);
+}
+
+}  // namespace gt

@@ -205,26 +205,30 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t* kin, cons
   }
 }
 
-// Sort (key, val) pairs by the bits [bit_lo, bit_hi) of the key (ascending,
-// or descending with desc), stably. n = *num (device) <= cap. The input is
-// (k0, v0); (k1, v1) is scratch of the same size; the result lands in
-// (kout, vout). hist needs radix_hist_entries(cap) entries. bit_hi - bit_lo
-// is rounded up to whole bytes.
 inline int64_t radix_hist_entries(int64_t cap) {
   const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
   return 256 * (nb > 0 ? nb : 1) + scan_sums_entries(256 * (nb > 0 ? nb : 1));
 }
 
+// Sort (key, val) pairs stably by the key bytes set in byte_mask (bit i =
+// byte i; bytes outside the mask must be equal in all keys), ascending or
+// descending (desc). n = *num (device) <= cap. The input is (k0, v0); (k1, v1)
+// is scratch of the same size; the result lands in (kout, vout). hist needs
+// radix_hist_entries(cap) entries. At least one byte must be set.
 template <typename V>
-hipError_t radix_sort_pairs(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int64_t* num, int64_t cap, int bit_lo,
-                            int bit_hi, bool desc, uint32_t* hist, uint64_t* kout, V* vout, hipStream_t s) {
+hipError_t radix_sort_pairs_bytes(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int64_t* num, int64_t cap,
+                                  uint64_t byte_mask, bool desc, uint32_t* hist, uint64_t* kout, V* vout,
+                                  hipStream_t s) {
   const int nb = (int)((cap + kRadixTile - 1) / kRadixTile);
   if (nb == 0) return hipSuccess;
-  const int npass = (bit_hi - bit_lo + 7) / 8;
+  int shifts[8], npass = 0;
+  for (int b = 0; b < 8; ++b)
+    if (byte_mask >> b & 1) shifts[npass++] = 8 * b;
+  if (npass == 0) shifts[npass++] = 0;
   const uint64_t* ksrc = k0;
   const V* vsrc = v0;
   for (int p = 0; p < npass; ++p) {
-    const int shift = bit_lo + 8 * p;
+    const int shift = shifts[p];
     uint64_t* kdst = (p == npass - 1) ? kout : ((p & 1) == 0 ? k1 : k0);
     V* vdst = (p == npass - 1) ? vout : ((p & 1) == 0 ? v1 : v0);
     k_radix_hist<<<nb, 256, 0, s>>>(ksrc, num, shift, desc, hist, nb);
@@ -239,6 +243,15 @@ hipError_t radix_sort_pairs(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int6
     vsrc = vdst;
   }
   return hipSuccess;
+}
+
+// The same over the bits [bit_lo, bit_hi), rounded out to whole bytes.
+template <typename V>
+hipError_t radix_sort_pairs(uint64_t* k0, V* v0, uint64_t* k1, V* v1, const int64_t* num, int64_t cap, int bit_lo,
+                            int bit_hi, bool desc, uint32_t* hist, uint64_t* kout, V* vout, hipStream_t s) {
+  uint64_t mask = 0;
+  for (int b = bit_lo / 8; b * 8 < bit_hi && b < 8; ++b) mask |= 1ull << b;
+  return radix_sort_pairs_bytes<V>(k0, v0, k1, v1, num, cap, mask, desc, hist, kout, vout, s);
 }
 
 }  // namespace gt
