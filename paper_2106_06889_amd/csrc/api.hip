@@ -453,18 +453,6 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
   return GTADOC_OK;
 }
 
-int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
-  (void)stream;
-  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
-  return fail(GTADOC_ERR_UNSUPPORTED, "term vector: not available in this build");
-}
-
-int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
-  (void)stream;
-  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
-  return fail(GTADOC_ERR_UNSUPPORTED, "inverted index: not available in this build");
-}
-
 namespace {
 
 // Byte mask of the packed n-gram keys: word ids < V occupy bitlen(V-1) bits
@@ -493,6 +481,174 @@ gtadoc_result new_result(gtadoc_ctx ctx) {
 }
 
 }  // namespace
+
+namespace {
+
+// Term vector into arrays owned by `owner` (a result's blocks, or call
+// scratch for the inverted index): off[F+1], word[NNZ], cnt[NNZ].
+struct TvArrays {
+  int64_t* off = nullptr;
+  uint32_t* word = nullptr;
+  uint64_t* cnt = nullptr;
+  int64_t nnz = 0;
+};
+
+int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, TvArrays* out) {
+  const gt::DevGrammar& d = g->d;
+  hipStream_t s = call.stream();
+  const int64_t R = d.R, F = d.F;
+  if ((uint64_t)g->st.tokens >= (1ull << 32))
+    return fail(GTADOC_ERR_UNSUPPORTED, "term vector: counts beyond 2^32 tokens are not supported");
+  if (d.V > gt::kWcBucket * gt::kWcMaxBuckets)
+    return fail(GTADOC_ERR_UNSUPPORTED, "term vector: vocabularies above 2^24 words are not supported");
+  const int32_t nb = (int32_t)((d.V + gt::kWcBucket - 1) / gt::kWcBucket);
+  const int32_t D = (int32_t)g->st.depth;
+  // 1. bounds (bottom-up), table offsets by one scan (bump allocation); file units
+  auto* len = call.scratch<uint64_t>(R);
+  auto* bound = call.scratch<uint64_t>(R);
+  auto* toff = call.scratch<uint64_t>(R);
+  auto* tsize = call.scratch<uint32_t>(R);
+  auto* unit_off = call.scratch<int64_t>(F + 1);
+  auto* sums64 = call.scratch<uint64_t>(gt::scan_scratch_entries(std::max<int64_t>(R, F + 1)));
+  auto* tot = call.scratch<int64_t>(4);  // [0] pool entries, [1] units, [2] entries, [3] nnz
+  if (!len || !bound || !toff || !tsize || !unit_off || !sums64 || !tot) return oom("term vector scratch", 36ull * R);
+  HIP_TRY(gt::launch_fill_u64(len, R, 0, s));
+  HIP_TRY(gt::launch_fill_u64(bound, R, 0, s));
+  HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(tsize), R, 0, s));
+  HIP_TRY(gt::launch_fill_u64(reinterpret_cast<uint64_t*>(unit_off), F + 1, 0, s));
+  HIP_TRY(gt::launch_tv_bounds(d, g->level_off.data(), D, len, bound, s));
+  HIP_TRY(hipMemcpyAsync(toff, bound, 8 * R, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(gt::launch_scan_u64_ext(toff, R, tot + 0, sums64, s));
+  HIP_TRY(gt::launch_tv_units(d, unit_off, s));
+  HIP_TRY(gt::launch_scan_u64_ext(reinterpret_cast<uint64_t*>(unit_off), F + 1, tot + 1, sums64, s));
+  auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
+  HIP_TRY(hipMemcpyAsync(pc, tot, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t P = pc[0], NU = pc[1];
+  // 2. tables, children first
+  auto* pw = call.scratch<uint32_t>(P);
+  auto* pcnt = call.scratch<uint32_t>(P);
+  if (!pw || !pcnt) return oom("rule tables", 8ull * P);
+  HIP_TRY(gt::launch_tv_tables(d, g->level_off.data(), D, toff, tsize, pw, pcnt, s));
+  // 3. group every file's inputs by (file, word bucket)
+  gt::TvFiles t{};
+  t.unit_off = unit_off;
+  t.nunits = NU;
+  t.nb = nb;
+  t.toff = toff, t.tsize = tsize, t.pw = pw, t.pc = pcnt;
+  const int64_t ntab = (int64_t)nb * NU;
+  t.table = call.scratch<uint32_t>(ntab + 1);
+  auto* sums32 = call.scratch<uint32_t>(gt::scan_scratch_entries(std::max<int64_t>(ntab, F * (int64_t)nb)));
+  if (!t.table || !sums32) return oom("term vector table", 4ull * ntab);
+  HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(t.table), ntab + 1, 0, s));
+  HIP_TRY(gt::launch_tv_count(d, t, s));
+  HIP_TRY(gt::launch_scan_u32_ext(t.table, ntab, tot + 2, sums32, s));
+  HIP_TRY(hipMemcpyAsync(pc, tot + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t E = pc[0];
+  if (E >= (1ll << 32)) return fail(GTADOC_ERR_UNSUPPORTED, "term vector: more than 2^32 merge inputs");
+  auto* entries = call.scratch<uint64_t>(E);
+  auto* nnz = call.scratch<uint32_t>(F * (int64_t)nb + 1);
+  if (!entries || !nnz) return oom("term vector entries", 8ull * E);
+  HIP_TRY(gt::launch_tv_scatter(d, t, entries, s));
+  // 4. dense LDS sums per group, then the CSR
+  HIP_TRY(gt::launch_tv_reduce(d, t, entries, E, nnz, s));
+  auto* noff = call.scratch<uint32_t>(F * (int64_t)nb + 1);
+  if (!noff) return oom("term vector offsets", 4ull * F * nb);
+  HIP_TRY(hipMemcpyAsync(noff, nnz, 4 * F * (int64_t)nb, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(gt::launch_scan_u32_ext(noff, F * (int64_t)nb, tot + 3, sums32, s));
+  HIP_TRY(hipMemcpyAsync(pc, tot + 3, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t NNZ = pc[0];
+  TvArrays a;
+  a.nnz = NNZ;
+  if (owner) {
+    a.off = call.keep<int64_t>(F + 1, *owner);
+    a.word = call.keep<uint32_t>(NNZ, *owner);
+    a.cnt = call.keep<uint64_t>(NNZ, *owner);
+  } else {
+    a.off = call.scratch<int64_t>(F + 1);
+    a.word = call.scratch<uint32_t>(NNZ);
+    a.cnt = call.scratch<uint64_t>(NNZ);
+  }
+  if (!a.off || !a.word || !a.cnt) return oom("term vector result", 12ull * NNZ);
+  HIP_TRY(gt::launch_tv_emit(d, t, entries, E, nnz, noff, a.word, a.cnt, a.off, s));
+  HIP_TRY(gt::launch_fill_u64(reinterpret_cast<uint64_t*>(a.off + F), 1, (uint64_t)NNZ, s));
+  *out = a;
+  return GTADOC_OK;
+}
+
+}  // namespace
+
+int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  gtadoc_result res = new_result(g->ctx);
+  if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  TvArrays a;
+  rc = term_vector_into(g, call, &res->blocks, &a);
+  if (rc) {
+    (void)hipStreamSynchronize(call.stream());
+    release_all(g->ctx, res->blocks);
+    delete res;
+    return rc;
+  }
+  res->a[0] = {a.off, g->d.F + 1, 8};
+  res->a[1] = {a.word, a.nnz, 4};
+  res->a[2] = {a.cnt, a.nnz, 8};
+  res->na = 3;
+  *out = res;
+  return GTADOC_OK;
+}
+
+int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  TvArrays a;
+  rc = term_vector_into(g, call, nullptr, &a);
+  if (rc) return rc;
+  const int64_t NNZ = a.nnz;
+  const int32_t V = g->d.V;
+  gtadoc_result res = new_result(g->ctx);
+  if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  auto* ii_off = call.keep<int64_t>((int64_t)V + 1, res->blocks);
+  auto* file = call.keep<uint32_t>(NNZ, res->blocks);
+  auto* k0 = call.scratch<uint64_t>(NNZ);
+  auto* k1 = call.scratch<uint64_t>(NNZ);
+  auto* kout = call.scratch<uint64_t>(NNZ);
+  auto* v0 = call.scratch<uint32_t>(NNZ);
+  auto* v1 = call.scratch<uint32_t>(NNZ);
+  auto* hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(NNZ));
+  auto* num = call.scratch<int64_t>(1);
+  if (!ii_off || !file || !k0 || !k1 || !kout || !v0 || !v1 || !hist || !num) {
+    (void)hipStreamSynchronize(s);
+    release_all(g->ctx, res->blocks);
+    delete res;
+    return oom("inverted index", 40ull * NNZ);
+  }
+  hipError_t e = gt::launch_fill_u64(reinterpret_cast<uint64_t*>(num), 1, (uint64_t)NNZ, s);
+  if (e == hipSuccess)
+    e = gt::launch_ii(a.off, g->d.F, a.word, NNZ, V, k0, v0, k1, v1, kout, file, num, hist, ii_off, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    release_all(g->ctx, res->blocks);
+    delete res;
+    return fail(GTADOC_ERR_HIP, "inverted index: %s", hipGetErrorString(e));
+  }
+  res->a[0] = {ii_off, (int64_t)V + 1, 8};
+  res->a[1] = {file, NNZ, 4};
+  res->na = 2;
+  *out = res;
+  return GTADOC_OK;
+}
+
+
 
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");

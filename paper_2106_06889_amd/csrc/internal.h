@@ -119,6 +119,35 @@ struct SortScratch {
 };
 int64_t sort_scratch_hist_entries(int64_t n);
 
+// term vector / inverted index
+struct TvFiles {
+  const int64_t* unit_off;  // [F+1] first kTileSyms-unit of every file
+  int64_t nunits;
+  int32_t nb;               // word buckets
+  uint32_t* table;          // [nb * nunits] counts, then offsets
+  const uint64_t* toff;     // rule table offsets in the pool
+  const uint32_t* tsize;    // rule table sizes
+  const uint32_t* pw;       // pool: words
+  const uint32_t* pc;       // pool: counts
+};
+hipError_t launch_tv_bounds(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
+                            uint64_t* bound, hipStream_t s);
+hipError_t launch_tv_tables(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, const uint64_t* toff,
+                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, hipStream_t s);
+hipError_t launch_tv_units(const DevGrammar& g, int64_t* units, hipStream_t s);
+hipError_t launch_tv_count(const DevGrammar& g, const TvFiles& t, hipStream_t s);
+hipError_t launch_tv_scatter(const DevGrammar& g, const TvFiles& t, uint64_t* entries, hipStream_t s);
+hipError_t launch_tv_reduce(const DevGrammar& g, const TvFiles& t, uint64_t* entries, int64_t E, uint32_t* nnz,
+                            hipStream_t s);
+hipError_t launch_tv_emit(const DevGrammar& g, const TvFiles& t, const uint64_t* entries, int64_t E,
+                          const uint32_t* nnz, const uint32_t* noff, uint32_t* out_word, uint64_t* out_cnt,
+                          int64_t* out_off, hipStream_t s);
+hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, int64_t nnz, int32_t V,
+                     uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout, uint32_t* file_out,
+                     const int64_t* num, uint32_t* hist, int64_t* ii_off, hipStream_t s);
+hipError_t launch_scan_u64_ext(uint64_t* a, int64_t n, int64_t* total, uint64_t* sums, hipStream_t s);
+hipError_t launch_scan_u32_ext(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
+
 // sequence count
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
                            int32_t* head, int32_t* tail, hipStream_t s);

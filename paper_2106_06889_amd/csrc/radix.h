@@ -118,6 +118,110 @@ inline hipError_t launch_scan_u32(uint32_t* a, int64_t n, int64_t* total, uint32
   return hipGetLastError();
 }
 
+// 64-bit exclusive scan (same three phases) for offsets that may pass 2^32.
+static __global__ __attribute__((unused)) __launch_bounds__(1024) void k_scan_u64_single(uint64_t* a, int64_t n,
+                                                                                        int64_t* total) {
+  __shared__ uint64_t wsum[16];
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = threadIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  uint64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += a[i];
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint64_t x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) base += wsum[w];
+    tot += wsum[w];
+  }
+  uint64_t run = base + x - s;
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint64_t c = a[i];
+    a[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0 && total) *total = (int64_t)tot;
+}
+
+__device__ __forceinline__ uint64_t block_exclusive_scan_256_u64(uint64_t v, uint64_t* lds, uint64_t* total) {
+  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wave] = x;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint64_t c = lds[w];
+    if (w < wave) base += c;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+static __global__ __attribute__((unused)) __launch_bounds__(256) void k_scan_sums_u64(const uint64_t* a, int64_t n,
+                                                                                      uint64_t* sums) {
+  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
+  uint64_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) c += a[i0 + k];
+  __shared__ uint64_t lds[4];
+  uint64_t total;
+  block_exclusive_scan_256_u64(c, lds, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+static __global__ __attribute__((unused)) __launch_bounds__(256) void k_scan_apply_u64(uint64_t* a, int64_t n,
+                                                                                       const uint64_t* sums) {
+  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
+  uint64_t v[16], c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = (i0 + k < n) ? a[i0 + k] : 0ull;
+    c += v[k];
+  }
+  __shared__ uint64_t lds[4];
+  uint64_t total;
+  uint64_t run = sums[blockIdx.x] + block_exclusive_scan_256_u64(c, lds, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) {
+      a[i0 + k] = run;
+      run += v[k];
+    }
+}
+
+// In-place exclusive scan of uint64 values; `sums` needs scan_sums_entries(n).
+inline hipError_t launch_scan_u64(uint64_t* a, int64_t n, int64_t* total, uint64_t* sums, hipStream_t s) {
+  const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+  if (nb <= 1) {
+    k_scan_u64_single<<<1, 1024, 0, s>>>(a, n, total);
+    return hipGetLastError();
+  }
+  k_scan_sums_u64<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_u64_single<<<1, 1024, 0, s>>>(sums, nb, total);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan_apply_u64<<<(unsigned)nb, 256, 0, s>>>(a, n, sums);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ uint32_t radix_digit(uint64_t k, int shift, bool desc) {
   return (uint32_t)(((desc ? ~k : k) >> shift) & 0xffu);
 }

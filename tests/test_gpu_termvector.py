@@ -1,0 +1,110 @@
+"""GPU parity: term vector and inverted index through the C ABI against the
+oracle (per-file top-down traversal and brute force), bit-exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2106_06889_amd as gt
+    assert torch.cuda.is_available()
+    c = gt.Context(4 << 30)
+    yield c
+    c.close()
+
+
+def gpu_tv(G):
+    import paper_2106_06889_amd as gt
+    res = G.term_vector()
+    off = res.arrays[0].cpu().numpy()
+    word = res.arrays[1].cpu().numpy().view(np.uint32)
+    cnt = gt.to_u64(res.arrays[2])
+    res.free()
+    return off, word, cnt
+
+
+def gpu_ii(G):
+    res = G.inverted_index()
+    off = res.arrays[0].cpu().numpy()
+    files = res.arrays[1].cpu().numpy().view(np.uint32)
+    res.free()
+    return off, files
+
+
+def check(ctx, g, brute=True):
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        off, word, cnt = gpu_tv(G)
+        woff, wword, wcnt = oracle.traverse_term_vector(g)
+        assert np.array_equal(off, woff)
+        assert np.array_equal(word, wword)
+        assert np.array_equal(cnt, wcnt)
+        if brute:
+            boff, bword, bcnt = oracle.brute_term_vector(g)
+            assert np.array_equal(off, boff) and np.array_equal(word, bword) and np.array_equal(cnt, bcnt)
+        ioff, ifile = gpu_ii(G)
+        woff2, wfile = oracle.inverted_index(woff, wword, g.vocab)
+        assert np.array_equal(ioff, woff2) and np.array_equal(ifile, wfile)
+    finally:
+        G.free()
+
+
+def test_golden_e2(ctx):
+    with open(os.path.join(GOLD, "e2_two_files.json")) as f:
+        d = json.load(f)
+    g = synth.Grammar(np.array(d["grammar"]["rule_off"], np.int64), np.array(d["grammar"]["sym"], np.int32),
+                      np.array(d["grammar"]["file_off"], np.int64), d["vocab"])
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    off, word, cnt = gpu_tv(G)
+    assert off.tolist() == d["term_vector"]["off"]
+    assert word.tolist() == d["term_vector"]["word"] and cnt.tolist() == d["term_vector"]["cnt"]
+    ioff, ifile = gpu_ii(G)
+    assert ioff.tolist() == d["inverted_index"]["off"] and ifile.tolist() == d["inverted_index"]["file"]
+    G.free()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_corpora(ctx, seed):
+    c = synth.random_corpus(200 + seed, 1 + 2 * (seed % 5), 2500, [3, 11, 500][seed % 3])
+    check(ctx, synth.compress(c.tokens, c.file_off, c.vocab))
+
+
+def test_long_bodies_and_empty_files(ctx):
+    """Bodies longer than the merge's register cursors, repeated children,
+    empty files, an unreachable rule."""
+    rng = np.random.default_rng(5)
+    V = 40
+    r1 = rng.integers(0, V, 5).astype(np.int32)                      # R1: 5 words
+    r2 = np.concatenate([rng.integers(0, V, 30), [-1, -1, -1]]).astype(np.int32)  # R2: 33 symbols, R1 x3
+    r3 = np.array([-2, 7, -1, -2], np.int32)                            # R3: R2 twice, R1
+    r4 = np.array([1, 2, 3], np.int32)                                 # R4: unreachable
+    f0 = np.array([-3, 5, -1], np.int32)
+    f2 = np.concatenate([rng.integers(0, V, 25), [-2, -3, -1]]).astype(np.int32)
+    root = np.concatenate([f0, f2])
+    sym = np.concatenate([root, r1, r2, r3, r4])
+    lens = [len(root), len(r1), len(r2), len(r3), len(r4)]
+    rule_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    file_off = np.array([0, len(f0), len(f0), len(root), len(root)], np.int64)  # files 1 and 3 empty
+    g = synth.Grammar(rule_off, sym, file_off, V)
+    assert oracle.check_structure(g) == 0
+    check(ctx, g)
+
+
+def test_tv_recipe_scaled(ctx):
+    c, g = synth.workload("tv-4000files", scale=0.01)  # 40 files
+    check(ctx, g, brute=False)
+
+
+def test_wc_recipe_single_file(ctx):
+    c, g = synth.workload("wc-200k")
+    check(ctx, g)
