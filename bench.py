@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
-"""Benchmark: uncompressed words/s analysed by word count (+ sort) on a
-Sequitur-compressed synthetic corpus resident in HBM, on one MI355X.
+"""Benchmark of exact analytics on Sequitur-compressed synthetic corpora
+resident in HBM, on one MI355X.
 
-One step = the whole path from the compressed grammar in device memory to
-the final results: load (validation, in-degrees, level frontiers, top-down
-weights), word count, sort. Inputs are generated and compressed on the host
-before timing and copied to the GPU once.
-
-Prints one JSON line (last line of stdout).
+Default (`--query wc`): uncompressed words/s analysed by word count (+ sort).
+One step = the whole path from the compressed grammar in device memory to the
+final results: load (validation, in-degrees, level frontiers, top-down
+weights), word count, sort. Other modes:
+  --query sc     step = load + sequence count n = 2 and n = 3 (nested-repeat corpus)
+  --query tv     step = load + term vector + inverted index (4,000 files)
+  --query serve  256 resident grammars, Poisson query stream, continuous
+                 batching vs one query per call (p50/p99 latency)
+Inputs are generated and compressed on the host before timing and copied to
+the GPU once. Prints one JSON line (last line of stdout).
 """
 from __future__ import annotations
 
@@ -21,56 +25,82 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+DEFAULT_WORKLOAD = {"wc": "wc-100m", "sc": "seq-20m", "tv": "tv-4000files"}
+METRIC = {"wc": "uncompressed words/s analysed (word count)",
+          "sc": "uncompressed words/s analysed (sequence count, n = 2 and 3)",
+          "tv": "uncompressed words/s analysed (term vector + inverted index)"}
+STEP = {"wc": "load (validate, levels, weights) + word count + sort",
+        "sc": "load + sequence count n=2 + sequence count n=3",
+        "tv": "load + term vector + inverted index"}
 
 
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def describe(name: str) -> str:
+def describe(name: str, query: str) -> str:
     import synth
     s = synth.WORKLOADS[name]
-    return (f"{name}: {s.files} file(s), {s.tokens} tokens, vocab {s.vocab} Zipf({s.zipf_s}), "
-            f"{int(s.copy_frac * 100)}% span repeats of {s.span_min}-{s.span_max} tokens, Sequitur grammar "
-            f"resident in HBM; step = load (validate, levels, weights) + word count + sort")
+    shape = (f"{s.motif_chains} nested motif chains of {s.motif_levels} levels" if s.kind == 1 else
+             f"{int(s.copy_frac * 100)}% span repeats of {s.span_min}-{s.span_max} tokens"
+             + (" from earlier files" if s.cross_file else ""))
+    return (f"{name}: {s.files} file(s), {s.tokens if s.files == 1 else '~lognormal sizes'} tokens, vocab {s.vocab} "
+            f"Zipf({s.zipf_s}), {shape}, Sequitur grammar resident in HBM; step = {STEP[query]}")
 
 
-def cpu_baseline(g, tokens: int, budget_s: float) -> dict:
-    """The oracle's sequential DAG-traversal word count on the host, repeated
-    within a time budget on the full grammar."""
+def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
+    """The oracle's sequential DAG traversal on the host (one core), repeated
+    within a time budget on the full grammar (word count, sequence count) or
+    run over the leading files until the budget is spent (term vector: the
+    oracle traverses file by file)."""
+    import numpy as np
     import oracle
+    import synth
+    T = int(file_tokens.sum())
     t0 = time.perf_counter()
+    if query == "tv":
+        F = g.num_files
+        f, chunk = 0, max(1, F // 400)
+        while f < F and time.perf_counter() - t0 < budget_s:
+            hi = min(F, f + chunk)
+            oracle.traverse_term_vector(synth.Grammar(g.rule_off, g.sym, g.file_off[f:hi + 1], g.vocab))
+            f = hi
+        el = time.perf_counter() - t0
+        toks = int(file_tokens[:f].sum())
+        return {"value": toks / el, "unit": "words/s", "cores": 1, "kind": "oracle",
+                "sample": f"per-file top-down traversal term vector of the first {f} of {F} files "
+                          f"({toks} tokens) in {el:.1f} s"}
     reps = 0
     while True:
-        oracle.traverse_word_count(g)
+        if query == "wc":
+            oracle.traverse_word_count(g)
+        else:
+            oracle.traverse_sequence_count(g, 2)
+            oracle.traverse_sequence_count(g, 3)
         reps += 1
         el = time.perf_counter() - t0
         if el > budget_s or reps >= 20:
             break
     per = el / reps
-    return {"value": tokens / per, "unit": "words/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole grammar, {reps} run(s) of the sequential traversal word count, {per:.3f} s each"}
+    what = "word count" if query == "wc" else "sequence count n=2 and n=3"
+    return {"value": T / per, "unit": "words/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole grammar, {reps} run(s) of the sequential traversal {what}, {per:.3f} s each"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="wc-100m")
-    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
-        sys.exit(2)
+def roofline(name: str, nbytes: float, us: float) -> dict:
+    achieved = nbytes / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": int(nbytes),
+            "avg_us": us}
 
+
+def run_query(args):
     import numpy as np
     import synth
     t0 = time.time()
     c, g = synth.workload(args.workload, args.scale)
     T = len(c.tokens)
+    file_tokens = np.diff(c.file_off)
     log(f"corpus {args.workload} x{args.scale}: T={T} F={g.num_files} -> grammar R={g.num_rules} S={len(g.sym)} "
         f"({time.time() - t0:.1f}s)")
     del c
@@ -83,8 +113,14 @@ def main():
     sym = torch.from_numpy(g.sym).to(dev)
     fo = torch.from_numpy(g.file_off).to(dev)
     V = g.vocab
-    R, S = g.num_rules, len(g.sym)
+    R, S, F = g.num_rules, len(g.sym), g.num_files
+    root_syms = int(g.rule_off[1] - g.rule_off[0])
+    q = args.query
     arena = 64 * R + 8 * S + 64 * V + (64 << 20)
+    if q == "sc":
+        arena += 64 * S + 48 * R
+    if q == "tv":
+        arena += 48 * T // 10 + 64 * S + 64 * R + 16 * V + (1 << 30)
     ctx = gt.Context(arena, dev)
     counts = torch.empty(V, dtype=torch.int64, device=dev)
     ids = torch.empty(V, dtype=torch.int32, device=dev)
@@ -93,16 +129,26 @@ def main():
     lib = gt.lib()
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+    sizes = {}
 
-    def step(ev=None):
+    def step():
         G = ctx.load(ro, sym, fo, V, borrow=True)
-        if ev is not None:
-            ev[0].record(stream)
-        gt.gtadoc._check(lib.gtadoc_word_count(G.handle, counts.data_ptr(), sp))
-        if ev is not None:
-            ev[1].record(stream)
-        gt.gtadoc._check(lib.gtadoc_sort(G.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
-                                         num.data_ptr(), sp))
+        if q == "wc":
+            gt.gtadoc._check(lib.gtadoc_word_count(G.handle, counts.data_ptr(), sp))
+            gt.gtadoc._check(lib.gtadoc_sort(G.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
+                                             num.data_ptr(), sp))
+        elif q == "sc":
+            for n in (2, 3):
+                res = G.sequence_count(n)
+                sizes[f"U{n}"] = res.length(0)
+                res.free()
+        else:
+            res = G.term_vector()
+            sizes["nnz_tv"] = res.length(1)
+            res.free()
+            res = G.inverted_index()
+            sizes["nnz_ii"] = res.length(1)
+            res.free()
         G.free()
 
     for i in range(args.warmup):
@@ -110,39 +156,71 @@ def main():
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    # sanity: exact against the grammar's own token count
+    # sanity: exact totals against the grammar's own token count
     G = ctx.load(ro, sym, fo, V, borrow=True)
     st = G.stats
+    if q == "wc":
+        total = int(gt.to_u64(G.word_count()).sum())
+        assert total == T, (total, T)
+    elif q == "sc":
+        lens = file_tokens
+        for n in (2, 3):
+            res = G.sequence_count(n)
+            tot = int(gt.to_u64(res.arrays[1]).sum())
+            res.free()
+            want = int(np.maximum(lens - n + 1, 0).sum())
+            assert tot == want, (n, tot, want)
+    else:
+        res = G.term_vector()
+        tot = int(gt.to_u64(res.arrays[2]).sum())
+        res.free()
+        assert tot == T, (tot, T)
     G.free()
     assert st["tokens"] == T, (st["tokens"], T)
-    total = int(gt.to_u64(counts).sum())
-    assert total == T, (total, T)
     log(f"stats: {st}")
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ctx.set_param(gt.PARAM_TIMING, 1)
+    for ph in gt.PHASES:
+        ctx.phase_time(ph, reset=True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step()
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    ctx.set_param(gt.PARAM_TIMING, 0)
     ms_step = 1e3 * t_total / args.steps
-    wc_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    log(f"{args.steps} steps in {t_total:.3f}s ({ms_step:.3f} ms/step); word-count call {wc_ms * 1e3:.1f} us")
+    phases = {}
+    for ph in gt.PHASES:
+        ms, n = ctx.phase_time(ph)
+        if n:
+            phases[ph] = {"avg_us": 1e3 * ms / n, "count": n}
+    log(f"{args.steps} steps in {t_total:.3f}s ({ms_step:.3f} ms/step); phases {phases}")
 
-    # algorithmic bytes of the word-count pass: symbols, rule offsets, weights, counts
+    # algorithmic bytes of each timed kernel (what the method must move):
+    #   level walk  : non-root bodies, rule offsets, weights written, level order written
+    #   word count  : all bodies, rule offsets, weights, counts written
+    #   seq windows : all bodies, rule offsets, weights, len, head+tail, the distinct (key, count) pairs
+    #   tv tables   : non-root bodies, rule offsets, the per-rule tables written (8 B per entry)
     wc_bytes = 4 * S + 8 * (R + 1) + 8 * R + 8 * V
-    achieved = wc_bytes / (wc_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "word count pass (gtadoc_word_count)", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes": wc_bytes}
+    lv_bytes = 4 * (S - root_syms) + 8 * (R + 1) + 8 * R + 4 * R
+    cands = {"levels": ("level walk (k_levels)", lv_bytes),
+             "word_count": ("word count pass (bucket scatter + reduce)", wc_bytes)}
+    if q == "sc":
+        U = sizes.get("U2", 0) + sizes.get("U3", 0)
+        cands["seq_windows"] = ("owned windows into the exact table (k_seq_windows)",
+                                (2 * (4 * S + 8 * (R + 1) + 16 * R) + 8 * R + 16 * R + 16 * U) / 2)
+    dom = max((p for p in cands if p in phases), key=lambda p: phases[p]["avg_us"] * phases[p]["count"])
+    roof = roofline(cands[dom][0], cands[dom][1], phases[dom]["avg_us"])
+    others = {p: roofline(cands[p][0], cands[p][1], phases[p]["avg_us"]) for p in cands if p in phases and p != dom}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
-        cpu = cpu_baseline(g, T, args.cpu_budget)
+        cpu = cpu_baseline(q, g, file_tokens, args.cpu_budget)
         log(f"cpu baseline {cpu['value']:.3e} words/s")
     out = {
-        "metric": "uncompressed words/s analysed (word count)",
+        "metric": METRIC[q],
         "value": T * args.steps / t_total,
         "unit": "words/s",
         "n_gpus": 1,
@@ -154,13 +232,103 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": describe(args.workload) if args.scale == 1.0 else f"{args.workload} x{args.scale}",
-                   "tokens": T, "rules": R, "symbols": S, "depth": st["depth"], "files": g.num_files,
-                   "vocab": V, "word_count_call_us": wc_ms * 1e3},
-        "roofline": roofline,
+        "config": {"workload": describe(args.workload, q) if args.scale == 1.0 else f"{args.workload} x{args.scale}",
+                   "tokens": T, "rules": R, "symbols": S, "root_symbols": root_syms, "depth": st["depth"],
+                   "files": F, "vocab": V, **sizes},
+        "roofline": roof,
+        "phases_us": {p: v["avg_us"] for p, v in phases.items()},
+        "roofline_other": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ serving
+def run_serve(args):
+    import numpy as np
+    import synth
+    t0 = time.time()
+    specs = synth.serving_specs(count=args.grammars, scale=args.scale)
+    pairs = synth.serving_grammars(specs, workers=args.workers)
+    totT = sum(t for _, t in pairs)
+    log(f"{len(pairs)} grammars, sum T = {totT} ({time.time() - t0:.1f}s)")
+
+    import torch
+    import paper_2106_06889_amd as gt
+    from paper_2106_06889_amd import serve
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    gbytes = sum(16 * len(g.sym) + 80 * g.num_rules + 16 * g.num_files for g, _ in pairs)
+    biggest = max(t for _, t in pairs)
+    arena = gbytes + 64 * biggest + 16 * sum(len(g.sym) for g, _ in pairs) // 4 + (2 << 30)
+    ctx = gt.Context(arena, dev)
+    loaded = [ctx.load(g.rule_off, g.sym, g.file_off, g.vocab) for g, _ in pairs]
+    torch.cuda.synchronize()
+    log(f"loaded; arena in use {ctx.usage()[0] / 2**30:.2f} GiB of {arena / 2**30:.2f}")
+    srv = serve.Server(ctx, loaded, max_batch=args.max_batch)
+    # warm up every query kind once on a few grammars
+    srv.run(serve.poisson_trace(64, 0, len(loaded), seed=1), realtime=False)
+    srv.run_plain(serve.poisson_trace(32, 0, len(loaded), seed=2), realtime=False)
+    torch.cuda.synchronize()
+
+    # closed-loop capacity of the served system: every query present at t = 0
+    closed = serve.poisson_trace(args.queries, 0, len(loaded), seed=synth.SEED_BASE + 6)
+    t1 = time.perf_counter()
+    srv.run(closed, realtime=False)
+    cap = args.queries / (time.perf_counter() - t1)
+    t1 = time.perf_counter()
+    srv.run_plain(closed, realtime=False)
+    cap_plain = args.queries / (time.perf_counter() - t1)
+    log(f"closed-loop capacity: served {cap:.1f} q/s, plain {cap_plain:.1f} q/s")
+    loads = {}
+    for frac in (0.70, 0.95):
+        rate = frac * cap
+        trace = serve.poisson_trace(args.queries, rate, len(loaded), seed=synth.SEED_BASE + 7)
+        span = trace[-1].arrival
+        a = serve.percentiles(srv.run(trace))
+        b = serve.percentiles(srv.run_plain(trace))
+        loads[f"{frac:.2f}C"] = {"rate_qps": rate, "trace_s": span, "served": a, "plain": b}
+        log(f"lambda={frac:.2f}C ({rate:.0f} q/s): served p50 {a['p50_ms']:.2f} p99 {a['p99_ms']:.2f} ms; "
+            f"plain p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms")
+    srv.close()
+    mean_T = totT / len(pairs)
+    out = {
+        "metric": "served queries/s at saturation (closed loop, mixed word count / term vector / bigram)",
+        "value": cap, "unit": "queries/s", "n_gpus": 1, "steps": args.queries, "warmup": 96,
+        "ms_per_step": 1e3 / cap, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{len(pairs)} resident grammars, sizes log-uniform 1e4-2e7 tokens x{args.scale}, "
+                               f"sum T = {totT}; queries 50% word count, 30% term vector, 20% bigram count",
+                   "max_batch": args.max_batch, "plain_capacity_qps": cap_plain,
+                   "served_words_per_s": cap * mean_T},
+        "latency": loads,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--query", choices=("wc", "sc", "tv", "serve"), default="wc")
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grammars", type=int, default=256, help="serve: resident grammars")
+    ap.add_argument("--queries", type=int, default=2000, help="serve: queries per trace")
+    ap.add_argument("--max-batch", type=int, default=64, help="serve: word counts per batch")
+    ap.add_argument("--workers", type=int, default=16, help="serve: host processes generating grammars")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
+        sys.exit(2)
+    if args.query == "serve":
+        run_serve(args)
+        return
+    args.workload = args.workload or DEFAULT_WORKLOAD[args.query]
+    run_query(args)
 
 
 if __name__ == "__main__":

@@ -163,6 +163,54 @@ int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream);
  * vocab > 2^21), OVERFLOW, OOM, HIP. */
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream);
 
+/* ---- tunables (read by the autotuner; per context) ---------------------- */
+#define GTADOC_PARAM_WC_CHUNK 1          /* word-count reduce: entries per work item (>= 1024) */
+#define GTADOC_PARAM_BATCH_BLOCKS_PER_CU 2  /* batched word count: persistent scatter workgroups per CU */
+#define GTADOC_PARAM_BATCH_GRAPH 3       /* 1: replay a batch's launch sequence from a captured hipGraph */
+
+#define GTADOC_PARAM_TIMING 4          /* 1: record HIP events around the main kernels of every call */
+
+/* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
+int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);
+int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value);
+
+/* ---- kernel timing (GTADOC_PARAM_TIMING) ------------------------------------
+ * With timing on, every call records a pair of HIP events on its stream
+ * around each of the phases below; gtadoc_ctx_phase_time waits for the
+ * recorded events and returns the summed device time (ms) and the number of
+ * timed occurrences, optionally resetting them. */
+#define GTADOC_PHASE_LEVELS 0       /* load: the level walk (frontiers and top-down weights), one kernel */
+#define GTADOC_PHASE_WORD_COUNT 1   /* word count: bucket scatter + on-chip reduce */
+#define GTADOC_PHASE_SORT 2         /* sort: compaction + radix passes */
+#define GTADOC_PHASE_SEQ_WINDOWS 3  /* sequence count: owned windows into the exact hash table, one kernel */
+#define GTADOC_PHASE_TV_TABLES 4    /* term vector: bottom-up rule tables */
+#define GTADOC_PHASE_TV_REDUCE 5    /* term vector: per-file scatter + reduce */
+#define GTADOC_PHASE_LOAD 6         /* load: all device work after validation (degrees, levels, weights) */
+#define GTADOC_NUM_PHASES 7
+int gtadoc_ctx_phase_time(gtadoc_ctx ctx, int phase, double* total_ms, int64_t* count, int reset);
+
+/* ---- batched queries ------------------------------------------------------
+ * Many grammars of uneven size in one launch sequence: persistent kernels
+ * with a fixed grid walk a flattened list of work items (each grammar's
+ * blocks and chunks) described in device memory. The sequence is identical
+ * for every batch, so with GTADOC_PARAM_BATCH_GRAPH it is captured once into
+ * a hipGraph and replayed; only the descriptors change. */
+typedef struct gtadoc_batch_s* gtadoc_batch;
+
+/* A batch plan on ctx for up to max_items grammars whose word symbols total
+ * at most max_entries; its scratch is taken from the arena now. Errors:
+ * INVALID_ARG, OOM, HIP. */
+int gtadoc_batch_create(gtadoc_ctx ctx, int max_items, uint64_t max_entries, gtadoc_batch* out);
+
+/* Word count of gs[i] into counts[i] (device arrays of vocab_i uint64), for
+ * i < n, asynchronous on `stream`. Waits for the plan's previous batch
+ * before reusing its descriptors. Every grammar must belong to the plan's
+ * context and use the bucketed word count (vocab <= 2^24, tokens < 2^52).
+ * Errors: INVALID_ARG (n, sizes, foreign grammar), UNSUPPORTED, HIP. */
+int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* const* counts, int n, void* stream);
+
+int gtadoc_batch_destroy(gtadoc_batch b);
+
 /* Array `index` of a result: device pointer (inside the arena), element
  * count and element size in bytes. The result's sizes are final when the
  * producing call returns. Errors: INVALID_ARG. */

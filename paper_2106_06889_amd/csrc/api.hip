@@ -104,6 +104,33 @@ struct gtadoc_ctx_s {
   hipStream_t last = nullptr;    // stream of that call
   bool has_done = false;
   char* pinned = nullptr;        // small pinned host buffer for read-backs
+  int64_t wc_chunk = 32 * 1024;  // word-count reduce chunk (tunable)
+  int64_t batch_blocks_per_cu = 4;
+  int64_t batch_graph = 0;
+  int64_t param_epoch = 0;       // bumped on every parameter change (invalidates captured graphs)
+  int64_t timing = 0;            // record events around the main kernels of each call
+  struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // recorded, not yet read
+    std::vector<hipEvent_t> spare;
+    double ms = 0;
+    int64_t n = 0;
+  } timers[GTADOC_NUM_PHASES];
+};
+
+struct gtadoc_batch_s {
+  gtadoc_ctx ctx = nullptr;
+  std::vector<Block> blocks;
+  gt::BatchDesc* host = nullptr;   // pinned staging
+  gt::BatchDesc* dev = nullptr;    // in the arena
+  uint64_t* entries = nullptr;     // scratch in the arena
+  int max_items = 0;
+  uint64_t max_entries = 0;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;  // private stream the launch sequence is captured on
+  int64_t graph_epoch = -1;
 };
 
 struct gtadoc_grammar_s {
@@ -173,6 +200,65 @@ class Call {
   std::vector<Block> scratch_;
 };
 
+// Reads the recorded event pairs of a phase into its totals (waits for them).
+void fold_timer(gtadoc_ctx_s::Timer& t) {
+  for (auto& pr : t.pending) {
+    float ms = 0;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      t.ms += ms;
+      ++t.n;
+    }
+    t.spare.push_back(pr.first);
+    t.spare.push_back(pr.second);
+  }
+  t.pending.clear();
+}
+
+// HIP events around one phase of a call, on the call's stream, when the
+// context's timing is on. end() records the closing event; a scope left
+// without end() (an error path) records nothing.
+class PhaseScope {
+ public:
+  PhaseScope(gtadoc_ctx ctx, int phase, hipStream_t s) : ctx_(ctx), ph_(phase), s_(s) {
+    if (ctx_->timing) a_ = take();
+    if (a_ && hipEventRecord(a_, s_) != hipSuccess) give(a_), a_ = nullptr;
+  }
+  void end() {
+    if (!a_) return;
+    hipEvent_t b = take();
+    if (b && hipEventRecord(b, s_) == hipSuccess) {
+      auto& t = ctx_->timers[ph_];
+      t.pending.emplace_back(a_, b);
+      if (t.pending.size() > 4096) fold_timer(t);
+    } else {
+      give(a_);
+      if (b) give(b);
+    }
+    a_ = nullptr;
+  }
+  ~PhaseScope() {
+    if (a_) give(a_);
+  }
+
+ private:
+  hipEvent_t take() {
+    auto& sp = ctx_->timers[ph_].spare;
+    hipEvent_t e = nullptr;
+    if (!sp.empty()) {
+      e = sp.back();
+      sp.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  void give(hipEvent_t e) { ctx_->timers[ph_].spare.push_back(e); }
+  gtadoc_ctx ctx_;
+  int ph_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr;
+};
+
 int oom(const char* what, uint64_t bytes) {
   return fail(GTADOC_ERR_OOM, "arena exhausted allocating %s (%llu bytes)", what, (unsigned long long)bytes);
 }
@@ -215,6 +301,10 @@ int gtadoc_ctx_create(void* arena, uint64_t arena_bytes, gtadoc_ctx* out) {
 int gtadoc_ctx_destroy(gtadoc_ctx ctx) {
   if (!ctx) return fail(GTADOC_ERR_INVALID_ARG, "null context");
   if (ctx->has_done) (void)hipEventSynchronize(ctx->done);
+  for (auto& t : ctx->timers) {
+    fold_timer(t);
+    for (hipEvent_t e : t.spare) (void)hipEventDestroy(e);
+  }
   (void)hipEventDestroy(ctx->done);
   (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -296,8 +386,8 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   int32_t* level_cnt = call.scratch<int32_t>(R + 2);
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
-  uint32_t* sums = call.scratch<uint32_t>(
-      std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off), nbR + gt::scan_scratch_entries(nbR)}));
+  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
+                                                    nbR + gt::scan_scratch_entries(nbR) + 16}));
   if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc || !sums ||
       (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));
@@ -324,6 +414,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
                      (pc->status & gt::ST_EMPTY_BODY) ? "empty non-root rule body; " : "",
                      (pc->status & gt::ST_BAD_FILES) ? "file spans do not tile the root body" : ""));
   // phase 2: symbols, in-degrees, levels and weights
+  PhaseScope t_load(ctx, GTADOC_PHASE_LOAD, s);
   const bool atomic_degrees = d.rc_nb == 0;
   if (!hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
       (atomic_degrees && (!hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill") ||
@@ -342,8 +433,14 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     if (!hip_ok(gt::launch_in_degrees(d, pend, ref_entries, &lc->rc_entries, s), "in_degrees"))
       return bail(GTADOC_ERR_HIP);
   }
-  if (!hip_ok(gt::launch_levels(d, pend, level_cnt, lc, sums, ctx->device, s), "levels") ||
-      !hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
+  if (!hip_ok(gt::launch_level_frontier(d, pend, lc, sums, s), "levels"))
+    return bail(GTADOC_ERR_HIP);
+  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);
+  if (!hip_ok(gt::launch_level_walk(d, pend, level_cnt, lc, sums, ctx->device, s), "levels"))
+    return bail(GTADOC_ERR_HIP);
+  t_levels.end();
+  t_load.end();
+  if (!hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
   if (pc->status)
@@ -408,10 +505,14 @@ int word_count_into(gtadoc_grammar g, Call& call, uint64_t* counts) {
   if (d.wc_nb > 0 && (uint64_t)g->st.tokens < (1ull << (64 - gt::kWcBits))) {
     uint64_t* entries = call.scratch<uint64_t>(W);
     if (!entries) return oom("word entries", 8ull * W);
-    HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, s));
+    PhaseScope t(g->ctx, GTADOC_PHASE_WORD_COUNT, s);
+    HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, g->ctx->wc_chunk, s));
+    t.end();
     return GTADOC_OK;
   }
+  PhaseScope t(g->ctx, GTADOC_PHASE_WORD_COUNT, s);
   HIP_TRY(gt::launch_word_count(d, counts, s));
+  t.end();
   return GTADOC_OK;
 }
 }  // namespace
@@ -449,7 +550,9 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
   sc.capacity = V;
   if (!sc.key[0] || !sc.key[1] || !sc.val[0] || !sc.val[1] || !sc.hist || !sc.num) return oom("sort scratch", 24ull * V);
   const int key_bytes = std::max(1, (bitlen((uint64_t)g->st.tokens) + 7) / 8);
+  PhaseScope t_sort(g->ctx, GTADOC_PHASE_SORT, s);
   HIP_TRY(gt::launch_sort_by_count(word_counts, V, key_bytes, sc, ids, counts, num, s));
+  t_sort.end();
   return GTADOC_OK;
 }
 
@@ -529,7 +632,9 @@ int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, Tv
   auto* pw = call.scratch<uint32_t>(P);
   auto* pcnt = call.scratch<uint32_t>(P);
   if (!pw || !pcnt) return oom("rule tables", 8ull * P);
+  PhaseScope t_tables(g->ctx, GTADOC_PHASE_TV_TABLES, s);
   HIP_TRY(gt::launch_tv_tables(d, g->level_off.data(), D, toff, tsize, pw, pcnt, s));
+  t_tables.end();
   // 3. group every file's inputs by (file, word bucket)
   gt::TvFiles t{};
   t.unit_off = unit_off;
@@ -550,9 +655,11 @@ int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, Tv
   auto* entries = call.scratch<uint64_t>(E);
   auto* nnz = call.scratch<uint32_t>(F * (int64_t)nb + 1);
   if (!entries || !nnz) return oom("term vector entries", 8ull * E);
+  PhaseScope t_reduce(g->ctx, GTADOC_PHASE_TV_REDUCE, s);
   HIP_TRY(gt::launch_tv_scatter(d, t, entries, s));
   // 4. dense LDS sums per group, then the CSR
   HIP_TRY(gt::launch_tv_reduce(d, t, entries, E, nnz, s));
+  t_reduce.end();
   auto* noff = call.scratch<uint32_t>(F * (int64_t)nb + 1);
   if (!noff) return oom("term vector offsets", 4ull * F * nb);
   HIP_TRY(hipMemcpyAsync(noff, nnz, 4 * F * (int64_t)nb, hipMemcpyDeviceToDevice, s));
@@ -691,8 +798,10 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   auto* flags = call.scratch<int64_t>(2);  // [0] distinct keys, [1] overflow flag
   if (!keys || !vals || !cnt || !flags) return oom("sequence table", 16 * cap);
   HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(flags), 4, 0, s));
+  PhaseScope t_win(g->ctx, GTADOC_PHASE_SEQ_WINDOWS, s);
   HIP_TRY(gt::launch_seq_windows(d, n, g->seq_len, g->seq_head, g->seq_tail, keys, vals, cap,
                                  reinterpret_cast<uint32_t*>(flags + 1), s));
+  t_win.end();
   HIP_TRY(gt::launch_occ_count(keys, (int64_t)cap, cnt, flags, cnt + nb, s));
   auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
   HIP_TRY(hipMemcpyAsync(pc, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -728,6 +837,172 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   res->a[1] = {oval, U, 8};
   res->na = 2;
   *out = res;
+  return GTADOC_OK;
+}
+
+int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
+  if (!ctx) return fail(GTADOC_ERR_INVALID_ARG, "null context");
+  switch (param) {
+    case GTADOC_PARAM_WC_CHUNK:
+      if (value < 1024 || value > (1ll << 30)) return fail(GTADOC_ERR_INVALID_ARG, "chunk out of range");
+      ctx->wc_chunk = value;
+      break;
+    case GTADOC_PARAM_BATCH_BLOCKS_PER_CU:
+      if (value < 1 || value > 16) return fail(GTADOC_ERR_INVALID_ARG, "blocks per CU out of range");
+      ctx->batch_blocks_per_cu = value;
+      break;
+    case GTADOC_PARAM_BATCH_GRAPH:
+      ctx->batch_graph = value ? 1 : 0;
+      break;
+    case GTADOC_PARAM_TIMING:
+      ctx->timing = value ? 1 : 0;
+      return GTADOC_OK;  // changes no launch sequence
+    default:
+      return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
+  }
+  ++ctx->param_epoch;
+  return GTADOC_OK;
+}
+
+int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value) {
+  if (!ctx || !value) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  switch (param) {
+    case GTADOC_PARAM_WC_CHUNK: *value = ctx->wc_chunk; break;
+    case GTADOC_PARAM_BATCH_BLOCKS_PER_CU: *value = ctx->batch_blocks_per_cu; break;
+    case GTADOC_PARAM_BATCH_GRAPH: *value = ctx->batch_graph; break;
+    case GTADOC_PARAM_TIMING: *value = ctx->timing; break;
+    default: return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
+  }
+  return GTADOC_OK;
+}
+
+int gtadoc_ctx_phase_time(gtadoc_ctx ctx, int phase, double* total_ms, int64_t* count, int reset) {
+  if (!ctx || phase < 0 || phase >= GTADOC_NUM_PHASES) return fail(GTADOC_ERR_INVALID_ARG, "bad context or phase");
+  auto& t = ctx->timers[phase];
+  fold_timer(t);
+  if (total_ms) *total_ms = t.ms;
+  if (count) *count = t.n;
+  if (reset) t.ms = 0, t.n = 0;
+  return GTADOC_OK;
+}
+
+int gtadoc_batch_create(gtadoc_ctx ctx, int max_items, uint64_t max_entries, gtadoc_batch* out) {
+  if (!ctx || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (max_items < 1 || max_items > gt::kBatchMax) return fail(GTADOC_ERR_INVALID_ARG, "max_items out of range");
+  auto* b = new (std::nothrow) gtadoc_batch_s;
+  if (!b) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  b->ctx = ctx;
+  b->max_items = max_items;
+  b->max_entries = max_entries;
+  Block blk;
+  if (!ctx->arena.alloc(sizeof(gt::BatchDesc), &blk)) {
+    delete b;
+    return oom("batch descriptors", sizeof(gt::BatchDesc));
+  }
+  b->blocks.push_back(blk);
+  b->dev = reinterpret_cast<gt::BatchDesc*>(ctx->base + blk.off);
+  if (!ctx->arena.alloc(std::max<uint64_t>(max_entries, 1) * 8, &blk)) {
+    release_all(ctx, b->blocks);
+    delete b;
+    return oom("batch entries", 8 * max_entries);
+  }
+  b->blocks.push_back(blk);
+  b->entries = reinterpret_cast<uint64_t*>(ctx->base + blk.off);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(gt::BatchDesc), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    if (b->host) (void)hipHostFree(b->host);
+    release_all(ctx, b->blocks);
+    delete b;
+    return fail(GTADOC_ERR_HIP, "batch setup failed");
+  }
+  std::memset(b->host, 0, sizeof(gt::BatchDesc));
+  *out = b;
+  return GTADOC_OK;
+}
+
+int gtadoc_batch_destroy(gtadoc_batch b) {
+  if (!b) return fail(GTADOC_ERR_INVALID_ARG, "null batch");
+  if (b->launched) (void)hipEventSynchronize(b->done);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  (void)hipEventDestroy(b->done);
+  (void)hipHostFree(b->host);
+  release_all(b->ctx, b->blocks);
+  delete b;
+  return GTADOC_OK;
+}
+
+int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* const* counts, int n, void* stream) {
+  if (!b || (n > 0 && (!gs || !counts))) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (n < 0 || n > b->max_items) return fail(GTADOC_ERR_INVALID_ARG, "batch of %d exceeds the plan (%d)", n, b->max_items);
+  gtadoc_ctx ctx = b->ctx;
+  // descriptors are rewritten only after the plan's previous batch finished
+  if (b->launched && hipEventSynchronize(b->done) != hipSuccess) return fail(GTADOC_ERR_HIP, "batch wait failed");
+  gt::BatchDesc& h = *b->host;
+  h.n = n;
+  h.chunk = ctx->wc_chunk;
+  h.fill_base[0] = h.scatter_base[0] = h.reduce_base[0] = 0;
+  uint64_t used = 0;
+  for (int i = 0; i < n; ++i) {
+    const gtadoc_grammar g = gs[i];
+    if (!g || g->ctx != ctx || !counts[i]) return fail(GTADOC_ERR_INVALID_ARG, "item %d: null or foreign grammar", i);
+    if (g->d.wc_nb == 0 || (uint64_t)g->st.tokens >= (1ull << (64 - gt::kWcBits)))
+      return fail(GTADOC_ERR_UNSUPPORTED, "item %d: grammar needs the direct word count", i);
+    const int64_t W = g->st.word_syms;
+    gt::BatchItem& it = h.items[i];
+    it.g = g->d;
+    it.out = counts[i];
+    it.entries = b->entries + used;
+    it.W = W;
+    used += (uint64_t)W;
+    h.fill_base[i + 1] = h.fill_base[i] + (g->d.V + gt::kWcBucket - 1) / gt::kWcBucket;
+    h.scatter_base[i + 1] = h.scatter_base[i] + (W > 0 ? g->d.nblk : 0);
+    h.reduce_base[i + 1] = h.reduce_base[i] + (W + h.chunk - 1) / h.chunk;
+  }
+  if (used > b->max_entries)
+    return fail(GTADOC_ERR_INVALID_ARG, "batch needs %llu entries, plan holds %llu", (unsigned long long)used,
+                (unsigned long long)b->max_entries);
+  Call call(ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  const int grid_scatter = (int)(cus * ctx->batch_blocks_per_cu);
+  const int grid_reduce = cus;
+  // the launch sequence: descriptors to the device, then the persistent kernels
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(b->dev, b->host, sizeof(gt::BatchDesc), hipMemcpyHostToDevice, q);
+    if (e != hipSuccess) return e;
+    return gt::launch_word_count_batch(b->dev, grid_scatter, grid_reduce, gt::kWcMaxBuckets, q);
+  };
+  if (ctx->batch_graph) {
+    // captured once on the plan's own stream (the caller's may be the null
+    // stream, which cannot capture), replayed on the caller's stream; the
+    // copy node reads the pinned descriptors at each replay
+    if (!b->exec || b->graph_epoch != ctx->param_epoch) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec), b->exec = nullptr;
+      if (b->graph) (void)hipGraphDestroy(b->graph), b->graph = nullptr;
+      if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue(b->capture);
+      hipGraph_t graph = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(b->capture, &graph);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(GTADOC_ERR_HIP, "batch capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      b->graph = graph;
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_epoch = ctx->param_epoch;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, s));
+  } else {
+    HIP_TRY(enqueue(s));
+  }
+  HIP_TRY(hipEventRecord(b->done, s));
+  b->launched = true;
   return GTADOC_OK;
 }
 

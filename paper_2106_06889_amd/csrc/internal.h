@@ -101,13 +101,34 @@ hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t*
 hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s);
 // in-degrees and initial weights from the reference entries (after the offsets are scanned)
 hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entries, const int64_t* n, hipStream_t s);
-hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
-                         int device, hipStream_t s);
+// level 1 (rules no rule references) by compaction, then the level walk
+hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
+                                 hipStream_t s);
+hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
+                             uint32_t* scratch, int device, hipStream_t s);
 
 // word count and sort
 hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics
 hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint64_t* entries, int64_t W,
-                                     hipStream_t s);
+                                     int64_t chunk, hipStream_t s);
+// batched word count: descriptors in device memory
+constexpr int kBatchMax = 1024;
+struct BatchItem {
+  DevGrammar g;
+  uint64_t* out;       // [V] counts
+  uint64_t* entries;   // [W] scratch
+  int64_t W;
+};
+struct BatchDesc {
+  int32_t n;
+  int32_t pad;
+  int64_t chunk;                       // reduce chunk (entries per work item)
+  int64_t fill_base[kBatchMax + 1];    // prefix of ceil(V / 4096) per grammar
+  int64_t scatter_base[kBatchMax + 1]; // prefix of nblk
+  int64_t reduce_base[kBatchMax + 1];  // prefix of ceil(W / chunk)
+  BatchItem items[kBatchMax];
+};
+hipError_t launch_word_count_batch(const BatchDesc* d, int grid_scatter, int grid_reduce, int max_nb, hipStream_t s);
 hipError_t launch_scan_offsets(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
 int64_t scan_scratch_entries(int64_t n);
 struct SortScratch {

@@ -10,17 +10,14 @@
 //
 // Differences from the paper's design (same results): the rounds are not
 // relaunched from the host until a stop flag stays set. One cooperative
-// launch walks the levels with a grid barrier between them, and each level's
+// launch walks the levels with a grid barrier between wide levels (narrow
+// levels finish on a single workgroup), and each level's
 // ready rules are compacted into a frontier list (gathered per workgroup in
 // LDS, one global atomic per workgroup and level), so a round touches only
 // the rules of that level rather than scanning every rule's mask. In-degrees count occurrences (a rule used twice by the
 // same parent waits for both), which gives the same levels and weights.
-#include <hip/hip_cooperative_groups.h>
-
 #include "device.h"
 #include "radix.h"
-
-namespace cg = cooperative_groups;
 
 namespace gt {
 
@@ -390,66 +387,109 @@ __device__ __forceinline__ bool agg_add(LevelLds& L, int32_t c, uint64_t w) {
   return false;
 }
 
+// Grid barrier for the cooperative level walk: workgroups arrive on one of 8
+// counters (by XCD: workgroups are dispatched to the XCDs round-robin), the
+// last of each group arrives on the top counter, the last group bumps the
+// generation that everyone waits for. Release/acquire atomics at agent scope
+// order every workgroup's writes before the barrier with every read after
+// it. bar[0..7] group counters, bar[8] top counter, bar[9] generation; all
+// zero at launch.
+__device__ __forceinline__ void grid_barrier(uint32_t* bar, uint32_t& gen) {
+  __threadfence();  // every wave's own stores and atomics complete at device scope
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t n = gridDim.x, g0 = gen;
+    const uint32_t grp = blockIdx.x % kXcds;
+    const uint32_t grp_size = n / kXcds + (grp < n % kXcds ? 1u : 0u);
+    const uint32_t ngroups = n < (uint32_t)kXcds ? n : (uint32_t)kXcds;
+    const uint32_t a = __hip_atomic_fetch_add(&bar[grp], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == grp_size - 1) {
+      __hip_atomic_store(&bar[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t t = __hip_atomic_fetch_add(&bar[8], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == ngroups - 1) {
+        __hip_atomic_store(&bar[8], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&bar[9], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    while (__hip_atomic_load(&bar[9], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(2);
+  }
+  ++gen;
+  __syncthreads();
+  __threadfence();
+}
+
+// One level: rules level_rule[lo, hi) processed by `nthreads` threads (this
+// thread is `tid`); new members of level d+1 are appended after hi.
+__device__ __forceinline__ void level_round(DevGrammar& g, int32_t* pend, int32_t* level_cnt, LevelLds& L, int32_t lo,
+                                            int32_t hi, int32_t d, int64_t tid, int64_t nthreads, uint64_t& tokens) {
+  for (int64_t i = lo + tid; i < hi; i += nthreads) {
+    const int32_t p = g.level_rule[i];
+    const uint64_t wp = g.w[p];
+    const int64_t e = g.rule_off[p + 1];
+    uint64_t words = 0;
+    for (int64_t q = g.rule_off[p]; q < e; ++q) {
+      const int32_t s = g.sym[q];
+      bool ready = false;
+      int32_t c = 0;
+      if (s >= 0) {
+        ++words;
+      } else {
+        c = -s;
+        // out-of-range ids are reported by the scan and never touched here
+        if (c < g.R && !agg_add(L, c, wp)) {
+          if (wp) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)wp);
+          ready = atomicSub(&pend[c], 1) == 1;
+        }
+      }
+      level_append(ready, c, L, g, level_cnt, d, hi);
+    }
+    tokens += wp * words;
+  }
+  __syncthreads();
+  // apply the merged contributions
+  for (int slot = threadIdx.x; slot < kAggSlots; slot += blockDim.x) {
+    const int32_t c = L.key[slot];
+    bool ready = false;
+    if (c >= 0) {
+      const uint64_t dw = L.wsum[slot];
+      const int32_t dn = (int32_t)L.cnt[slot];
+      if (dw) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)dw);
+      ready = atomicSub(&pend[c], dn) == dn;
+      L.key[slot] = -1;
+      L.wsum[slot] = 0;
+      L.cnt[slot] = 0;
+    }
+    level_append(ready, c, L, g, level_cnt, d, hi);
+  }
+  __syncthreads();
+  const int32_t n_local = L.list_n < kLevelList ? L.list_n : kLevelList;
+  if (threadIdx.x == 0) L.list_base = n_local ? atomicAdd(&level_cnt[d + 1], n_local) : 0;
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < n_local; k += blockDim.x) g.level_rule[hi + L.list_base + k] = L.list[k];
+  if (threadIdx.x == 0) L.list_n = 0;
+}
+
+// Levels narrower than this finish on workgroup 0 alone (block barriers
+// instead of grid barriers); the other workgroups leave.
+constexpr int32_t kTailRules = 4 * kLevelThreads;
+
 __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt,
-                                                          LoadCounters* lc) {
-  cg::grid_group grid = cg::this_grid();
+                                                          LoadCounters* lc, uint32_t* bar) {
   __shared__ LevelLds L;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   int32_t lo = 0;
   int32_t hi = (int32_t)__hip_atomic_load(&lc->frontier0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int32_t d = 1;
+  uint32_t gen = 0;
   uint64_t tokens = 0;
   for (int i = threadIdx.x; i < kAggSlots; i += blockDim.x) L.key[i] = -1, L.wsum[i] = 0, L.cnt[i] = 0;
   if (threadIdx.x == 0) L.list_n = 0;
   __syncthreads();
-  while (lo < hi) {
-    for (int64_t i = lo + tid; i < hi; i += nthreads) {
-      const int32_t p = g.level_rule[i];
-      const uint64_t wp = g.w[p];
-      const int64_t e = g.rule_off[p + 1];
-      uint64_t words = 0;
-      for (int64_t q = g.rule_off[p]; q < e; ++q) {
-        const int32_t s = g.sym[q];
-        bool ready = false;
-        int32_t c = 0;
-        if (s >= 0) {
-          ++words;
-        } else {
-          c = -s;
-          // out-of-range ids are reported by the scan and never touched here
-          if (c < g.R && !agg_add(L, c, wp)) {
-            if (wp) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)wp);
-            ready = atomicSub(&pend[c], 1) == 1;
-          }
-        }
-        level_append(ready, c, L, g, level_cnt, d, hi);
-      }
-      tokens += wp * words;
-    }
-    __syncthreads();
-    // apply the merged contributions
-    for (int slot = threadIdx.x; slot < kAggSlots; slot += blockDim.x) {
-      const int32_t c = L.key[slot];
-      bool ready = false;
-      if (c >= 0) {
-        const uint64_t dw = L.wsum[slot];
-        const int32_t dn = (int32_t)L.cnt[slot];
-        if (dw) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)dw);
-        ready = atomicSub(&pend[c], dn) == dn;
-        L.key[slot] = -1;
-        L.wsum[slot] = 0;
-        L.cnt[slot] = 0;
-      }
-      level_append(ready, c, L, g, level_cnt, d, hi);
-    }
-    __syncthreads();
-    const int32_t n_local = L.list_n < kLevelList ? L.list_n : kLevelList;
-    if (threadIdx.x == 0) L.list_base = n_local ? atomicAdd(&level_cnt[d + 1], n_local) : 0;
-    __syncthreads();
-    for (int32_t k = threadIdx.x; k < n_local; k += blockDim.x) g.level_rule[hi + L.list_base + k] = L.list[k];
-    if (threadIdx.x == 0) L.list_n = 0;
-    grid.sync();
+  // wide levels: the whole grid, a grid barrier between levels
+  while (lo < hi && (hi - lo >= kTailRules || gridDim.x == 1)) {
+    level_round(g, pend, level_cnt, L, lo, hi, d, tid, nthreads, tokens);
+    grid_barrier(bar, gen);
     const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) {
       g.level_off[d] = lo;
@@ -458,6 +498,23 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
     lo = hi;
     hi += next;
     ++d;
+  }
+  // narrow levels: workgroup 0 alone
+  if (blockIdx.x == 0) {
+    while (lo < hi) {
+      level_round(g, pend, level_cnt, L, lo, hi, d, threadIdx.x, blockDim.x, tokens);
+      __threadfence();
+      __syncthreads();
+      const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0) {
+        g.level_off[d] = lo;
+        g.level_off[d + 1] = hi;
+      }
+      __syncthreads();
+      lo = hi;
+      hi += next;
+      ++d;
+    }
   }
   // block sum of the token contributions, one atomic per block
   tokens = wave_sum_u64(tokens);
@@ -474,8 +531,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   }
 }
 
-hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
-                         int device, hipStream_t s) {
+hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
+                                 hipStream_t s) {
   // level 1 by compaction (scratch: per-block counts, then the scan's block sums)
   const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
   k_zero_count<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch);
@@ -484,10 +541,14 @@ hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt,
   e = launch_scan_u32(scratch, nb, &lc->frontier0, scratch + nb, s);
   if (e != hipSuccess) return e;
   k_zero_write<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch, g.level_rule);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
+                             uint32_t* scratch, int device, hipStream_t s) {
+  const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
   int per_cu = 0, cus = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), kLevelThreads, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), kLevelThreads, 0);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
@@ -496,7 +557,10 @@ hipError_t launch_levels(const DevGrammar& g, int32_t* pend, int32_t* level_cnt,
   const int64_t cap = cus;  // one workgroup per CU: few participants in every grid barrier
   const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
   DevGrammar gg = g;
-  void* args[] = {&gg, &pend, &level_cnt, &lc};
+  uint32_t* bar = reinterpret_cast<uint32_t*>(scratch) + nb + scan_sums_entries(nb);  // 16 words after the scan's scratch
+  e = launch_fill_i32(reinterpret_cast<int32_t*>(bar), 16, 0, s);
+  if (e != hipSuccess) return e;
+  void* args[] = {&gg, &pend, &level_cnt, &lc, &bar};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(kLevelThreads), args, 0,
                                     s);
 }

@@ -47,16 +47,14 @@ __global__ __launch_bounds__(kTileThreads) void k_word_count(DevGrammar g, uint6
   }
 }
 
-// Scatter: one workgroup per block of kSubTiles tiles. LDS holds the block's
-// write cursor per bucket, starting at its offset from the load-time scan.
-__global__ __launch_bounds__(kTileThreads) void k_wc_scatter(DevGrammar g, uint64_t* entries) {
-  extern __shared__ int32_t lds_wc[];
-  int32_t* roff = lds_wc;
-  uint32_t* cursor = reinterpret_cast<uint32_t*>(lds_wc + kTileRuleSlots);
-  const int64_t slot = xcd_slot(blockIdx.x, g.nslot);
+// Scatter of block `blk` (kSubTiles tiles). LDS holds the block's write
+// cursor per bucket, starting at its offset from the load-time scan.
+__device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t blk, uint64_t* entries, int32_t* roff,
+                                                 uint32_t* cursor) {
+  const int64_t slot = xcd_slot(blk, g.nslot);
   for (int b = threadIdx.x; b < g.wc_nb; b += blockDim.x) cursor[b] = g.wc_off[(int64_t)b * g.nslot + slot];
   for (int sub = 0; sub < kSubTiles; ++sub) {
-    const int64_t tile = (int64_t)blockIdx.x * kSubTiles + sub;
+    const int64_t tile = blk * kSubTiles + sub;
     if (tile >= g.ntiles) break;  // uniform for the block
     const Tile t = tile_begin(g, tile, roff);
     const int32_t q0 = threadIdx.x * kPerThread;
@@ -81,24 +79,28 @@ __global__ __launch_bounds__(kTileThreads) void k_wc_scatter(DevGrammar g, uint6
         }
       }
     }
-    __syncthreads();  // roff is rewritten by the next tile
+    __syncthreads();  // roff (and the cursors, for the next block) are rewritten
   }
 }
 
-// Reduce: the entry array is cut into chunks of kWcChunk entries (bucket
-// sizes follow the word frequencies, so whole buckets per workgroup would
-// leave a few workgroups with most of the work). A workgroup sums each
-// bucket segment of its chunk in LDS -- kWcCopies copies of the bucket's
-// table, wave w using copy w % kWcCopies, so one frequent word's adds spread
-// over several addresses -- then adds the nonzero sums to the (zeroed) count
-// array with coalesced global atomics.
+__global__ __launch_bounds__(kTileThreads) void k_wc_scatter(DevGrammar g, uint64_t* entries) {
+  extern __shared__ int32_t lds_wc[];
+  wc_scatter_block(g, blockIdx.x, entries, lds_wc, reinterpret_cast<uint32_t*>(lds_wc + kTileRuleSlots));
+}
+
+// Reduce: the entry array is cut into chunks (bucket sizes follow the word
+// frequencies, so whole buckets per workgroup would leave a few workgroups
+// with most of the work). A workgroup sums each bucket segment of its chunk
+// in LDS -- kWcCopies copies of the bucket's table, wave w using copy
+// w % kWcCopies, so one frequent word's adds spread over several addresses --
+// then adds the nonzero sums to the (zeroed) count array with coalesced
+// global atomics.
 constexpr int kWcCopies = 4;
 constexpr int kWcThreads = 1024;
-constexpr int64_t kWcChunk = 32 * kWcThreads;
 
 // First bucket whose range [start(b), start(b+1)) holds entry i; start(b) =
-// off[b * nslot], start(nb) = n.
-__device__ __forceinline__ int bucket_of(const uint32_t* off, int64_t nslot, int nb, int64_t n, int64_t i) {
+// off[b * nslot].
+__device__ __forceinline__ int bucket_of(const uint32_t* off, int64_t nslot, int nb, int64_t i) {
   int lo = 0, hi = nb - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -108,17 +110,19 @@ __device__ __forceinline__ int bucket_of(const uint32_t* off, int64_t nslot, int
   return lo;
 }
 
-__global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const uint64_t* entries, int64_t W,
-                                                          uint64_t* counts) {
-  __shared__ uint64_t acc[kWcCopies][kWcBucket];
-  __shared__ int first_bucket;
-  for (int i = threadIdx.x; i < kWcCopies * kWcBucket; i += blockDim.x) (&acc[0][0])[i] = 0;
-  const int64_t c_lo = (int64_t)blockIdx.x * kWcChunk;
-  const int64_t c_hi = c_lo + kWcChunk < W ? c_lo + kWcChunk : W;
-  if (threadIdx.x == 0) first_bucket = bucket_of(g.wc_off, g.nslot, g.wc_nb, W, c_lo);
+struct WcReduceLds {
+  uint64_t acc[kWcCopies][kWcBucket];
+  int first_bucket;
+};
+
+__device__ __forceinline__ void wc_reduce_chunk(const DevGrammar& g, const uint64_t* entries, int64_t W,
+                                                uint64_t* counts, int64_t chunk_idx, int64_t chunk, WcReduceLds& L) {
+  const int64_t c_lo = chunk_idx * chunk;
+  const int64_t c_hi = c_lo + chunk < W ? c_lo + chunk : W;
+  if (threadIdx.x == 0) L.first_bucket = bucket_of(g.wc_off, g.nslot, g.wc_nb, c_lo);
   __syncthreads();
-  uint64_t* mine = acc[(threadIdx.x >> 6) % kWcCopies];
-  for (int b = first_bucket; b < g.wc_nb; ++b) {
+  uint64_t* mine = L.acc[(threadIdx.x >> 6) % kWcCopies];
+  for (int b = L.first_bucket; b < g.wc_nb; ++b) {
     const int64_t b_lo = g.wc_off[(int64_t)b * g.nslot];
     const int64_t b_hi = (b + 1 < g.wc_nb) ? (int64_t)g.wc_off[(int64_t)(b + 1) * g.nslot] : W;
     if (b_lo >= c_hi) break;
@@ -132,15 +136,24 @@ __global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const ui
     for (int i = threadIdx.x; i < kWcBucket; i += blockDim.x) {
       uint64_t sum = 0;
 #pragma unroll
-      for (int c = 0; c < kWcCopies; ++c) sum += acc[c][i], acc[c][i] = 0;
-      if (sum && base + i < g.V) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[base + i]), (unsigned long long)sum);
+      for (int c = 0; c < kWcCopies; ++c) sum += L.acc[c][i], L.acc[c][i] = 0;
+      if (sum && base + i < g.V)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&counts[base + i]), (unsigned long long)sum);
     }
     __syncthreads();
   }
 }
 
+__global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const uint64_t* entries, int64_t W,
+                                                          uint64_t* counts, int64_t chunk) {
+  __shared__ WcReduceLds L;
+  for (int i = threadIdx.x; i < kWcCopies * kWcBucket; i += blockDim.x) (&L.acc[0][0])[i] = 0;
+  __syncthreads();
+  wc_reduce_chunk(g, entries, W, counts, blockIdx.x, chunk, L);
+}
+
 hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint64_t* entries, int64_t W,
-                                     hipStream_t s) {
+                                     int64_t chunk, hipStream_t s) {
   hipError_t e = launch_fill_u64(counts, g.V, 0, s);
   if (e != hipSuccess) return e;
   if (g.ntiles == 0 || W == 0) return hipSuccess;
@@ -148,7 +161,72 @@ hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint
   k_wc_scatter<<<(unsigned)g.nblk, kTileThreads, shmem, s>>>(g, entries);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_wc_reduce<<<(unsigned)((W + kWcChunk - 1) / kWcChunk), kWcThreads, 0, s>>>(g, entries, W, counts);
+  k_wc_reduce<<<(unsigned)((W + chunk - 1) / chunk), kWcThreads, 0, s>>>(g, entries, W, counts, chunk);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched word count over many grammars: persistent kernels with a fixed grid
+// walk a flattened list of work items (item k of grammar i = its k-th block,
+// chunk or fill range) described in device memory. The launch sequence is the
+// same for every batch -- only the descriptors change -- so it can be
+// captured once in a hipGraph and replayed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int batch_item_owner(const int64_t* base, int n, int64_t it) {
+  int lo = 0, hi = n - 1;  // last i with base[i] <= it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_wcb_fill(const BatchDesc* d) {
+  const int n = d->n;
+  const int64_t total = d->fill_base[n];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int i = batch_item_owner(d->fill_base, n, it);
+    const BatchItem& b = d->items[i];
+    const int64_t lo = (it - d->fill_base[i]) * kWcBucket;
+    for (int64_t x = lo + threadIdx.x; x < lo + kWcBucket && x < b.g.V; x += blockDim.x) b.out[x] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_wcb_scatter(const BatchDesc* d) {
+  extern __shared__ int32_t lds_wcb[];
+  const int n = d->n;
+  const int64_t total = d->scatter_base[n];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int i = batch_item_owner(d->scatter_base, n, it);
+    const BatchItem& b = d->items[i];
+    wc_scatter_block(b.g, it - d->scatter_base[i], b.entries, lds_wcb,
+                     reinterpret_cast<uint32_t*>(lds_wcb + kTileRuleSlots));
+  }
+}
+
+__global__ __launch_bounds__(kWcThreads) void k_wcb_reduce(const BatchDesc* d) {
+  __shared__ WcReduceLds L;
+  for (int i = threadIdx.x; i < kWcCopies * kWcBucket; i += blockDim.x) (&L.acc[0][0])[i] = 0;
+  __syncthreads();
+  const int n = d->n;
+  const int64_t total = d->reduce_base[n];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int i = batch_item_owner(d->reduce_base, n, it);
+    const BatchItem& b = d->items[i];
+    wc_reduce_chunk(b.g, b.entries, b.W, b.out, it - d->reduce_base[i], d->chunk, L);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_word_count_batch(const BatchDesc* d, int grid_scatter, int grid_reduce, int max_nb, hipStream_t s) {
+  k_wcb_fill<<<grid_scatter, 256, 0, s>>>(d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_wcb_scatter<<<grid_scatter, kTileThreads, sizeof(int32_t) * (kTileRuleSlots + max_nb), s>>>(d);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_wcb_reduce<<<grid_reduce, kWcThreads, 0, s>>>(d);
   return hipGetLastError();
 }
 

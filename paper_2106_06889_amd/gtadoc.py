@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -58,8 +59,16 @@ EXPORTS = {
     "gtadoc_sequence_count": [_vp, _int, _vp, _vp],
     "gtadoc_result_array": [_vp, _int, _vp, _vp, _vp],
     "gtadoc_result_free": [_vp],
+    "gtadoc_ctx_set_param": [_vp, _int, _i64],
+    "gtadoc_ctx_get_param": [_vp, _int, _vp],
+    "gtadoc_batch_create": [_vp, _int, _u64, _vp],
+    "gtadoc_batch_word_count": [_vp, _vp, _vp, _int, _vp],
+    "gtadoc_batch_destroy": [_vp],
+    "gtadoc_ctx_phase_time": [_vp, _int, _vp, _vp, _int],
     "gtadoc_last_error": [],
 }
+PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING = 1, 2, 3, 4
+PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6}
 
 
 def lib() -> ctypes.CDLL:
@@ -106,9 +115,14 @@ class Context:
         with torch.cuda.device(self.device):
             _check(lib().gtadoc_ctx_create(self.arena.data_ptr(), int(arena_bytes), ctypes.byref(h)))
         self.handle = h
+        self._children = weakref.WeakSet()  # grammars, results and plans living in the arena
 
     def close(self):
+        """Release every grammar, result and batch plan still open on the
+        context, then the context (they must not outlive it)."""
         if self.handle:
+            for c in list(self._children):
+                c.free()
             lib().gtadoc_ctx_destroy(self.handle)
             self.handle = None
 
@@ -117,6 +131,23 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_param(self, param: int, value: int):
+        _check(lib().gtadoc_ctx_set_param(self.handle, int(param), int(value)))
+
+    def get_param(self, param: int) -> int:
+        v = _i64()
+        _check(lib().gtadoc_ctx_get_param(self.handle, int(param), ctypes.byref(v)))
+        return v.value
+
+    def phase_time(self, phase: str, reset: bool = False) -> tuple[float, int]:
+        """(summed device ms, occurrences) of a timed phase; needs PARAM_TIMING on."""
+        ms, n = ctypes.c_double(), _i64()
+        _check(lib().gtadoc_ctx_phase_time(self.handle, PHASES[phase], ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        return ms.value, n.value
+
+    def batch(self, max_items: int, max_entries: int) -> "Batch":
+        return Batch(self, max_items, max_entries)
 
     def usage(self) -> tuple[int, int, int]:
         a, b, c = _u64(), _u64(), _u64()
@@ -147,30 +178,37 @@ class Context:
         return Grammar(self, h, keep)
 
 
-@dataclass
+@dataclass(eq=False)
 class Result:
     arrays: list
     handle: object
     ctx: Context
 
+    def __post_init__(self):
+        self.ctx._children.add(self)
+
+    def length(self, index: int) -> int:
+        return int(self.arrays[index].numel())
+
     def free(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             lib().gtadoc_result_free(self.handle)
-            self.handle = None
+        self.handle = None
 
 
 class Grammar:
     def __init__(self, ctx: Context, handle, keep=()):
         self.ctx, self.handle, self._keep = ctx, handle, keep
+        ctx._children.add(self)
         st = Stats()
         _check(lib().gtadoc_grammar_stats(handle, ctypes.byref(st)))
         self.stats = st.as_dict()
         self.vocab = st.vocab
 
     def free(self):
-        if self.handle:
+        if self.handle and self.ctx.handle:
             lib().gtadoc_free_grammar(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -218,6 +256,37 @@ class Grammar:
 
     def sequence_count(self, n: int, stream=None) -> Result:
         return self._result(lib().gtadoc_sequence_count, n, stream=stream)
+
+
+class Batch:
+    """A batch plan: word counts of many grammars in one launch sequence."""
+
+    def __init__(self, ctx: Context, max_items: int, max_entries: int):
+        self.ctx = ctx
+        h = _vp()
+        _check(lib().gtadoc_batch_create(ctx.handle, int(max_items), int(max_entries), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+
+    def word_count(self, grammars, outs, stream=None):
+        n = len(grammars)
+        gs = (ctypes.c_void_p * max(n, 1))(*[g.handle.value for g in grammars])
+        os_ = (ctypes.c_void_p * max(n, 1))(*[o.data_ptr() for o in outs])
+        _check(lib().gtadoc_batch_word_count(self.handle, gs, os_, n, _stream_ptr(stream)))
+        return outs
+
+    def close(self):
+        if self.handle and self.ctx.handle:
+            lib().gtadoc_batch_destroy(self.handle)
+        self.handle = None
+
+    free = close
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_u64(t: torch.Tensor) -> np.ndarray:

@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
         ("motif_chains", ctypes.c_int32), ("motif_levels", ctypes.c_int32),
         ("motif_min", ctypes.c_int32), ("motif_max", ctypes.c_int32),
         ("motif_ext_max", ctypes.c_int32), ("motif_min_inserts", ctypes.c_int32),
-        ("seed", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64), ("normalize", ctypes.c_int32),
     ]
 
 
@@ -104,6 +104,7 @@ class CorpusSpec:
     motif_ext_max: int = 4
     motif_min_inserts: int = 2
     seed: int = SEED_BASE
+    normalize: int = 0
 
     def scaled(self, factor: float, name: str | None = None) -> "CorpusSpec":
         """Same recipe at a fraction of the size (tokens, or the number of files)."""
@@ -226,3 +227,42 @@ def random_corpus(seed: int, files: int, max_tokens: int, vocab: int, run_bias: 
         toks.extend(f)
         off.append(len(toks))
     return Corpus(np.asarray(toks, dtype=np.int32), np.asarray(off, dtype=np.int64), vocab)
+
+
+def serving_specs(count: int = 256, t_min: float = 1e4, t_max: float = 2e7, seed: int = SEED_BASE + 5,
+                  scale: float = 1.0) -> list[CorpusSpec]:
+    """The resident grammars of the serving workload: sizes log-uniform in
+    [t_min, t_max] tokens (times `scale`), max(1, round(T/50,000)) files of
+    lognormal sizes each, shared vocabulary 500,000 Zipf(1.0), 30% of each
+    file copied from spans of 8-256 tokens of earlier files."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(count):
+        T = int(round(np.exp(rng.uniform(np.log(t_min), np.log(t_max))) * scale))
+        T = max(T, 64)
+        F = max(1, int(round(T / 50_000)))
+        specs.append(CorpusSpec(f"serve-{k}", tokens=T, files=F, lognorm_median=T / F, lognorm_sigma=1.32,
+                                file_min=1, file_max=T, vocab=500_000, zipf_s=1.0, copy_frac=0.30,
+                                span_min=8, span_max=256, cross_file=1, seed=seed * 1000 + k, normalize=1))
+    return specs
+
+
+def _build_one(spec: CorpusSpec):
+    c = corpus(spec)
+    g = compress(c.tokens, c.file_off, c.vocab)
+    return g.rule_off, g.sym, g.file_off, g.vocab, len(c.tokens)
+
+
+def serving_grammars(specs: list[CorpusSpec], workers: int = 8) -> list[tuple[Grammar, int]]:
+    """Generate and compress the serving grammars in parallel processes;
+    returns (grammar, tokens) pairs in spec order."""
+    import multiprocessing as mp
+    build()  # make sure the library exists before forking
+    order = sorted(range(len(specs)), key=lambda i: -specs[i].tokens)  # biggest first
+    out = [None] * len(specs)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(processes=max(1, workers)) as pool:
+        for i, res in zip(order, pool.imap(_build_one, [specs[i] for i in order])):
+            ro, sym, fo, V, T = res
+            out[i] = (Grammar(ro, sym, fo, V), T)
+    return out

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -176,6 +177,7 @@ typedef struct {
   int32_t cross_file;      // 1: files copy only from earlier files' tokens
   int32_t motif_chains, motif_levels, motif_min, motif_max, motif_ext_max, motif_min_inserts;
   uint64_t seed;
+  int32_t normalize;       // kind 0, files > 1: scale the lognormal sizes to sum to `tokens`
 } synth_params;
 
 typedef struct {
@@ -198,6 +200,18 @@ static void gen_kind0(const synth_params& P, synth_corpus& C, Rng& rng, const Zi
   }
   int64_t total = 0;
   for (auto s : sizes) total += s;
+  if (F > 1 && P.normalize && P.tokens > 0 && total > 0) {
+    // keep the lognormal shape, rescale so the sizes sum to exactly `tokens`
+    int64_t acc = 0;
+    for (int f = 0; f < F; ++f) {
+      const int64_t t = (int64_t)((double)sizes[f] * (double)P.tokens / (double)total);
+      sizes[f] = std::max<int64_t>(1, t);
+      acc += sizes[f];
+    }
+    sizes[F - 1] = std::max<int64_t>(1, sizes[F - 1] + (P.tokens - acc));
+    total = 0;
+    for (auto s : sizes) total += s;
+  }
   C.tok.reserve((size_t)total);
   C.file_off.assign(1, 0);
   for (int f = 0; f < F; ++f) {
@@ -584,9 +598,19 @@ void* synth_sequitur(const int32_t* tok, const int64_t* file_off, int64_t num_fi
     for (int64_t i = 0; i < T; ++i)
       if (tok[i] < 0 || tok[i] >= vocab) return nullptr;
     Sequitur sq(vocab, (size_t)(T + num_files));
+    // large inputs report their progress on stderr (they take minutes)
+    const int64_t every = T >= (int64_t(1) << 27) ? (int64_t(1) << 26) : INT64_MAX;
+    int64_t next_report = every;
     for (int64_t f = 0; f < num_files; ++f) {
       if (f > 0) sq.append(vocab + (int32_t)(f - 1));  // unique splitter
-      for (int64_t i = file_off[f]; i < file_off[f + 1]; ++i) sq.append(tok[i]);
+      for (int64_t i = file_off[f]; i < file_off[f + 1]; ++i) {
+        sq.append(tok[i]);
+        if (i + 1 == next_report) {
+          std::fprintf(stderr, "[synth] sequitur %lld / %lld tokens\n", (long long)(i + 1), (long long)T);
+          std::fflush(stderr);
+          next_report += every;
+        }
+      }
     }
     // renumber: root = 0, then first encounter in a left-to-right preorder walk
     const size_t nr = sq.guard.size();
