@@ -118,7 +118,8 @@ def run_query(args):
     q = args.query
     arena = 64 * R + 8 * S + 64 * V + (64 << 20)
     if q == "sc":
-        arena += 64 * S + 48 * R
+        # exact table (16 B per slot, slots < 4 (n-1) S), results, sort scratch, head/tail/len
+        arena += 256 * S + 48 * R
     if q == "tv":
         arena += 48 * T // 10 + 64 * S + 64 * R + 16 * V + (1 << 30)
     ctx = gt.Context(arena, dev)
@@ -320,10 +321,22 @@ def main():
     ap.add_argument("--queries", type=int, default=2000, help="serve: queries per trace")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: word counts per batch")
     ap.add_argument("--workers", type=int, default=16, help="serve: host processes generating grammars")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+        return
     if args.query == "serve":
         run_serve(args)
         return

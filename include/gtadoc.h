@@ -169,6 +169,8 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
 #define GTADOC_PARAM_BATCH_GRAPH 3       /* 1: replay a batch's launch sequence from a captured hipGraph */
 
 #define GTADOC_PARAM_TIMING 4          /* 1: record HIP events around the main kernels of every call */
+#define GTADOC_PARAM_LEVEL_WIDE 5      /* load: levels of at least this many rules accumulate weights and
+                                          in-edges by bucket instead of atomics (0: never; default 262144) */
 
 /* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);

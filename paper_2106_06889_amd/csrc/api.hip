@@ -109,6 +109,7 @@ struct gtadoc_ctx_s {
   int64_t batch_graph = 0;
   int64_t param_epoch = 0;       // bumped on every parameter change (invalidates captured graphs)
   int64_t timing = 0;            // record events around the main kernels of each call
+  int64_t level_wide = 262144;   // level walk: bucketed mode from this many rules per level (0: never)
   struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // recorded, not yet read
     std::vector<hipEvent_t> spare;
@@ -387,7 +388,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
   uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
-                                                    nbR + gt::scan_scratch_entries(nbR) + 16}));
+                                                    nbR + gt::scan_scratch_entries(nbR)}));
   if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc || !sums ||
       (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));
@@ -413,6 +414,22 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
                      (pc->status & gt::ST_BAD_OFFSETS) ? "rule offsets not monotone in [0, S]; " : "",
                      (pc->status & gt::ST_EMPTY_BODY) ? "empty non-root rule body; " : "",
                      (pc->status & gt::ST_BAD_FILES) ? "file spans do not tile the root body" : ""));
+  // scratch of the level walk's bucketed mode (wide levels); without room
+  // for it every level takes the atomic mode
+  gt::WideBufs wide{};
+  {
+    const int64_t nbk = (R + gt::kWideBucket - 1) / gt::kWideBucket;
+    const int64_t nonroot = S - pc->root_syms;
+    if (ctx->level_wide > 0 && nbk <= gt::kWideMaxBuckets && nonroot > 0 && nonroot < (1ll << 32)) {
+      wide.ew = call.scratch<uint64_t>(nonroot);
+      wide.ec = call.scratch<uint16_t>(nonroot);
+      wide.cur = call.scratch<uint32_t>(nbk);
+      wide.seg_lo = call.scratch<uint32_t>(nbk);
+      wide.nbk = (int32_t)nbk;
+      wide.min_rules = (int32_t)std::min<int64_t>(ctx->level_wide, INT32_MAX);
+      if (!wide.ew || !wide.ec || !wide.cur || !wide.seg_lo) wide = gt::WideBufs{};
+    }
+  }
   // phase 2: symbols, in-degrees, levels and weights
   PhaseScope t_load(ctx, GTADOC_PHASE_LOAD, s);
   const bool atomic_degrees = d.rc_nb == 0;
@@ -436,7 +453,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   if (!hip_ok(gt::launch_level_frontier(d, pend, lc, sums, s), "levels"))
     return bail(GTADOC_ERR_HIP);
   PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);
-  if (!hip_ok(gt::launch_level_walk(d, pend, level_cnt, lc, sums, ctx->device, s), "levels"))
+  if (!hip_ok(gt::launch_level_walk(d, pend, level_cnt, lc, sums, wide, ctx->device, s), "levels"))
     return bail(GTADOC_ERR_HIP);
   t_levels.end();
   t_load.end();
@@ -467,7 +484,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   st.rules = R;
   st.files = F;
   st.word_syms = (int64_t)pc->word_syms;
-  st.root_syms = 0;
+  st.root_syms = pc->root_syms;
   st.depth = D;
   st.vocab = V;
   uint64_t bytes = 0;
@@ -857,6 +874,10 @@ int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
     case GTADOC_PARAM_TIMING:
       ctx->timing = value ? 1 : 0;
       return GTADOC_OK;  // changes no launch sequence
+    case GTADOC_PARAM_LEVEL_WIDE:
+      if (value < 0) return fail(GTADOC_ERR_INVALID_ARG, "level width threshold out of range");
+      ctx->level_wide = value;
+      return GTADOC_OK;  // read at load time only
     default:
       return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
@@ -871,6 +892,7 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value) {
     case GTADOC_PARAM_BATCH_BLOCKS_PER_CU: *value = ctx->batch_blocks_per_cu; break;
     case GTADOC_PARAM_BATCH_GRAPH: *value = ctx->batch_graph; break;
     case GTADOC_PARAM_TIMING: *value = ctx->timing; break;
+    case GTADOC_PARAM_LEVEL_WIDE: *value = ctx->level_wide; break;
     default: return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
   return GTADOC_OK;

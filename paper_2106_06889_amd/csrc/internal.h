@@ -85,6 +85,25 @@ struct LoadCounters {
   int64_t frontier0;     // rules of level 1
   int64_t wc_entries;    // word entries counted into wc_off (= W)
   int64_t rc_entries;    // reference entries counted into rc_off (= S - W)
+  int64_t root_syms;     // length of the root body
+  int64_t wide_entries;  // references from non-root bodies (capacity of the wide-level entries)
+};
+
+// Buffers of the bucketed mode of the level walk (wide levels): the
+// references of every non-root body, grouped by the referenced rule's bucket
+// of kWideBucket consecutive ids; bucket b owns [off[b], off[b+1]) of ew/ec,
+// filled level after level (cur[b] = end of what is written, seg_lo[b] = end
+// of what is reduced). ew == nullptr disables the mode.
+constexpr int kWideBits = 12;
+constexpr int kWideBucket = 1 << kWideBits;
+constexpr int kWideMaxBuckets = 16384;
+struct WideBufs {
+  uint64_t* ew;      // weight of the referencing rule
+  uint16_t* ec;      // referenced rule id & (kWideBucket - 1)
+  uint32_t* cur;     // [nbk]
+  uint32_t* seg_lo;  // [nbk]
+  int32_t nbk;
+  int32_t min_rules;  // levels with at least this many rules use the bucketed mode
 };
 
 // ---------------------------------------------------------------------------
@@ -105,7 +124,7 @@ hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entri
 hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
                                  hipStream_t s);
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
-                             uint32_t* scratch, int device, hipStream_t s);
+                             uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s);
 
 // word count and sort
 hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics

@@ -67,7 +67,7 @@ EXPORTS = {
     "gtadoc_ctx_phase_time": [_vp, _int, _vp, _vp, _int],
     "gtadoc_last_error": [],
 }
-PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING = 1, 2, 3, 4
+PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING, PARAM_LEVEL_WIDE = 1, 2, 3, 4, 5
 PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6}
 
 

@@ -95,6 +95,41 @@ def test_wc_100m_recipe_scaled(ctx):
     check_wc_sort(ctx, g, expect_tokens=len(c.tokens))
 
 
+@pytest.mark.parametrize("wide", [0, 1, 4096, 20000])
+def test_level_walk_modes(ctx, wide):
+    """The level walk's bucketed mode (levels of at least `wide` rules; 0 =
+    never, 1 = every level) gives the same weights, levels and counts."""
+    import paper_2106_06889_amd as gt
+    cases = [synth.workload("wc-100m", scale=0.03), synth.workload("seq-20m", scale=0.02)]
+    for seed in (3, 4, 5):
+        c = synth.random_corpus(seed, 1 + seed % 3, 4000, [5, 60, 700][seed % 3])
+        cases.append((c, synth.compress(c.tokens, c.file_off, c.vocab)))
+    old = ctx.get_param(gt.PARAM_LEVEL_WIDE)
+    ctx.set_param(gt.PARAM_LEVEL_WIDE, wide)
+    try:
+        for c, g in cases:
+            st = check_wc_sort(ctx, g, expect_tokens=len(c.tokens))
+            assert st["root_syms"] == int(g.rule_off[1])
+            post = oracle.postorder(g)
+            assert st["depth"] == longest_path_levels(g)
+            assert len(post) == g.num_rules
+    finally:
+        ctx.set_param(gt.PARAM_LEVEL_WIDE, old)
+
+
+def longest_path_levels(g):
+    """Number of rule levels below the root: the longest root-to-rule path
+    (rules only), by a pass over the oracle's postorder reversed."""
+    post = oracle.postorder(g)
+    depth = np.zeros(g.num_rules, np.int64)
+    for r in post[::-1]:
+        body = g.sym[g.rule_off[r]:g.rule_off[r + 1]]
+        kids = -body[body < 0]
+        if len(kids):
+            np.maximum.at(depth, kids, depth[r] + 1)
+    return int(depth.max())
+
+
 def test_tile_boundaries(ctx):
     """Bodies that straddle many tile boundaries: a long non-root rule and a
     root longer than several tiles, with a ragged tail."""
