@@ -286,8 +286,10 @@ def run_serve(args):
         rate = frac * cap
         trace = serve.poisson_trace(args.queries, rate, len(loaded), seed=synth.SEED_BASE + 7)
         span = trace[-1].arrival
-        a = serve.percentiles(srv.run(trace))
-        b = serve.percentiles(srv.run_plain(trace))
+        ra, rb = srv.run(trace), srv.run_plain(trace)
+        a, b = serve.percentiles(ra), serve.percentiles(rb)
+        a["by_kind"] = {k: serve.percentiles([r for r in ra if r.kind == k]) for k in serve.KINDS}
+        b["by_kind"] = {k: serve.percentiles([r for r in rb if r.kind == k]) for k in serve.KINDS}
         loads[f"{frac:.2f}C"] = {"rate_qps": rate, "trace_s": span, "served": a, "plain": b}
         log(f"lambda={frac:.2f}C ({rate:.0f} q/s): served p50 {a['p50_ms']:.2f} p99 {a['p99_ms']:.2f} ms; "
             f"plain p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms")

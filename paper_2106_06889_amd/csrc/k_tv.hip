@@ -62,117 +62,341 @@ hipError_t launch_tv_bounds(const DevGrammar& g, const int32_t* level_off_host, 
   return hipSuccess;
 }
 
-// Table of rule r = merge of its pieces (own words, each counting 1, and the
-// sorted tables of its children, once per occurrence), emitted in word order.
-// Short bodies keep one cursor per piece in registers; long bodies locate
-// each piece's next word by binary search.
-constexpr int kTvCursors = 16;
+// Table of rule r = the merge of its pieces (own words, each counting 1, and
+// the sorted tables of its children, once per occurrence), in word order.
+// The merge of one rule is spread over a wave or a workgroup, never one
+// thread: a serial merge costs one dependent load per output entry, which is
+// milliseconds for the large tables near the top of the DAG. Per level, a
+// classification pass counts each rule's merge inputs n_in (own words plus
+// its children's table sizes) and sorts the rules into two lists:
+//  - n_in <= kTvWaveMax: one wave per rule gathers the inputs into LDS,
+//    bitonic-sorts them by word, and writes one entry per distinct word with
+//    the summed count;
+//  - larger: one workgroup per rule walks the word space in windows of 4096
+//    ids; each piece keeps a cursor, the window's inputs of every piece are
+//    summed in a dense LDS table, and its nonzero slots come out in order.
+constexpr int kTvWaveMax = 2048;   // inputs merged by one wave in LDS
+constexpr int kTvWaveWaves = 4;    // waves per workgroup of the wave merge
+constexpr int kTvBigThreads = 1024;
+constexpr int kTvBigPieces = 4096;  // body symbols the workgroup merge keeps cursors for
 
-__device__ __forceinline__ uint32_t first_above(const uint32_t* w, uint32_t n, int64_t x) {
-  uint32_t lo = 0, hi = n;  // first index with w[i] > x
-  while (lo < hi) {
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t first_at_least(const uint32_t* w, uint32_t lo, uint32_t hi, uint32_t x) {
+  while (lo < hi) {  // first index in [lo, hi) with w[i] >= x
     const uint32_t mid = (lo + hi) >> 1;
-    if ((int64_t)w[mid] > x) hi = mid;
+    if (w[mid] >= x) hi = mid;
     else lo = mid + 1;
   }
   return lo;
 }
 
-__global__ void k_tv_merge_level(DevGrammar g, const int32_t* rules, int32_t n, const uint64_t* toff, uint32_t* tsize,
-                                 uint32_t* pw, uint32_t* pc) {
+__global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t* rules, int32_t n,
+                                                     const uint32_t* tsize, int32_t* list_wave, int32_t* list_big,
+                                                     int32_t* counts) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t r = rules[i];
-  const int64_t a = g.rule_off[r];
-  const int64_t k = g.rule_off[r + 1] - a;
-  const uint64_t out = toff[r];
-  uint32_t m = 0;
-  if (k <= kTvCursors) {
-    int32_t sj[kTvCursors];
-    uint32_t cur[kTvCursors], lim[kTvCursors];
-    uint64_t base[kTvCursors];
+  const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  uint64_t n_in = 0;
+  for (int64_t q0 = a; q0 < b; q0 += 8) {
+    int32_t v[8];
 #pragma unroll
-    for (int j = 0; j < kTvCursors; ++j) {
-      sj[j] = j < k ? g.sym[a + j] : 0;
-      cur[j] = 0;
-      if (j < k && sj[j] < 0) {
-        lim[j] = tsize[-sj[j]];
-        base[j] = toff[-sj[j]];
-      } else {
-        lim[j] = (j < k) ? 1u : 0u;  // a word piece holds one entry
-        base[j] = 0;
+    for (int k = 0; k < 8; ++k) v[k] = q0 + k < b ? g.sym[q0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (q0 + k < b) n_in += v[k] >= 0 ? 1u : tsize[-v[k]];
+  }
+  if (n_in <= (uint64_t)kTvWaveMax) list_wave[atomicAdd(&counts[0], 1)] = r;
+  else list_big[atomicAdd(&counts[1], 1)] = r;
+}
+
+__global__ __launch_bounds__(64 * kTvWaveWaves) void k_tv_merge_wave(DevGrammar g, const int32_t* list,
+                                                                     const int32_t* count, const uint64_t* toff,
+                                                                     uint32_t* tsize, uint32_t* pw, uint32_t* pc) {
+  __shared__ uint64_t buf[kTvWaveWaves][kTvWaveMax];  // (word << 32 | count) per input
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  uint64_t* e = buf[wave];
+  const int32_t nr = *count;
+  for (int64_t j = (int64_t)blockIdx.x * kTvWaveWaves + wave; j < nr; j += (int64_t)gridDim.x * kTvWaveWaves) {
+    const int32_t r = list[j];
+    const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+    // gather: 64 pieces at a time, their sizes and sources loaded by the lanes
+    uint32_t n = 0;
+    for (int64_t q0 = a; q0 < b; q0 += 64) {
+      const int64_t q = q0 + lane;
+      const int32_t s = q < b ? g.sym[q] : 0;
+      const uint32_t size = q >= b ? 0u : (s >= 0 ? 1u : tsize[-s]);
+      const uint64_t src = (q < b && s < 0) ? toff[-s] : 0;
+      uint32_t incl = size;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
       }
-    }
-    while (true) {
-      uint32_t best = 0xffffffffu;
-#pragma unroll
-      for (int j = 0; j < kTvCursors; ++j) {
-        if (cur[j] < lim[j]) {
-          const uint32_t wd = sj[j] >= 0 ? (uint32_t)sj[j] : pw[base[j] + cur[j]];
-          best = wd < best ? wd : best;
+      const uint32_t at = n + incl - size;
+      const int np = (int)(b - q0 < 64 ? b - q0 : 64);
+      for (int pp = 0; pp < np; ++pp) {
+        const int32_t sp = __shfl(s, pp);
+        const uint32_t tp = __shfl(size, pp), ap = __shfl(at, pp);
+        const uint64_t op = __shfl(src, pp);
+        if (sp >= 0) {
+          if (lane == 0) e[ap] = ((uint64_t)(uint32_t)sp << 32) | 1u;
+        } else {
+          for (uint32_t x = lane; x < tp; x += 64) e[ap + x] = ((uint64_t)pw[op + x] << 32) | pc[op + x];
         }
       }
-      if (best == 0xffffffffu) break;
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int j = 0; j < kTvCursors; ++j) {
-        if (cur[j] < lim[j]) {
-          if (sj[j] >= 0) {
-            if ((uint32_t)sj[j] == best) ++cnt, ++cur[j];
-          } else if (pw[base[j] + cur[j]] == best) {
-            cnt += pc[base[j] + cur[j]];
-            ++cur[j];
+      n += __shfl(incl, 63);
+    }
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    for (uint32_t x = n + lane; x < P; x += 64) e[x] = ~0ull;
+    wave_lds_sync();
+    // bitonic sort, ascending
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t x = lane; x < P; x += 64) {
+          const uint32_t l = x ^ jj;
+          if (l > x) {
+            const uint64_t u = e[x], v = e[l];
+            if ((u > v) == ((x & k) == 0)) e[x] = v, e[l] = u;
           }
         }
+        wave_lds_sync();
       }
-      pw[out + m] = best;
-      pc[out + m] = cnt;
-      ++m;
     }
-  } else {
-    int64_t last = -1;
-    while (true) {
-      uint32_t best = 0xffffffffu;
-      for (int64_t j = 0; j < k; ++j) {
-        const int32_t s = g.sym[a + j];
-        if (s >= 0) {
-          if ((int64_t)s > last && (uint32_t)s < best) best = (uint32_t)s;
-        } else {
-          const uint32_t* w = pw + toff[-s];
-          const uint32_t t = tsize[-s];
-          const uint32_t x = first_above(w, t, last);
-          if (x < t && w[x] < best) best = w[x];
-        }
-      }
-      if (best == 0xffffffffu) break;
-      uint32_t cnt = 0;
-      for (int64_t j = 0; j < k; ++j) {
-        const int32_t s = g.sym[a + j];
-        if (s >= 0) {
-          cnt += (uint32_t)s == best;
-        } else {
-          const uint32_t* w = pw + toff[-s];
-          const uint32_t t = tsize[-s];
-          const uint32_t x = first_above(w, t, last);
-          if (x < t && w[x] == best) cnt += pc[toff[-s] + x];
-        }
-      }
-      pw[out + m] = best;
-      pc[out + m] = cnt;
-      ++m;
-      last = best;
+    // one output entry per distinct word: lanes take consecutive chunks
+    const uint32_t C = (n + 63) / 64;
+    const uint32_t c0 = lane * C < n ? lane * C : n, c1 = c0 + C < n ? c0 + C : n;
+    uint32_t h = 0;
+    for (uint32_t x = c0; x < c1; ++x) h += x == 0 || (e[x] >> 32) != (e[x - 1] >> 32);
+    uint32_t incl = h;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
     }
+    uint32_t o = incl - h;
+    const uint64_t out = toff[r];
+    for (uint32_t x = c0; x < c1; ++x) {
+      const uint32_t wd = (uint32_t)(e[x] >> 32);
+      if (x == 0 || wd != (uint32_t)(e[x - 1] >> 32)) {
+        uint32_t sum = 0;
+        for (uint32_t y = x; y < n && (uint32_t)(e[y] >> 32) == wd; ++y) sum += (uint32_t)e[y];
+        pw[out + o] = wd;
+        pc[out + o] = sum;
+        ++o;
+      }
+    }
+    if (lane == 63) tsize[r] = incl;
+    wave_lds_sync();  // the next rule reuses the buffer
+  }
+}
+
+// Exclusive scan over a 1024-thread workgroup (16 waves); *total gets the sum.
+__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t* lds16, uint32_t* total) {
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) lds16[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    const uint32_t c = lds16[w];
+    if (w < (int)(threadIdx.x >> 6)) base += c;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__device__ __forceinline__ uint32_t block_min_1024(uint32_t v, uint32_t* lds16) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t y = __shfl_xor(v, o);
+    v = y < v ? y : v;
+  }
+  if (lane_id() == 0) lds16[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t m = 0xffffffffu;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) m = lds16[w] < m ? lds16[w] : m;
+  __syncthreads();
+  return m;
+}
+
+// Serial merge by binary search (rules with more than kTvBigPieces body
+// symbols; never produced by Sequitur in practice, kept for completeness).
+__device__ void tv_merge_serial(const DevGrammar& g, int32_t r, const uint64_t* toff, uint32_t* tsize, uint32_t* pw,
+                                uint32_t* pc) {
+  const int64_t a = g.rule_off[r], k = g.rule_off[r + 1] - a;
+  const uint64_t out = toff[r];
+  uint32_t m = 0;
+  uint32_t next = 0;  // smallest word not yet emitted
+  while (true) {
+    uint32_t best = 0xffffffffu;
+    for (int64_t j = 0; j < k; ++j) {
+      const int32_t s = g.sym[a + j];
+      if (s >= 0) {
+        if ((uint32_t)s >= next && (uint32_t)s < best) best = (uint32_t)s;
+      } else {
+        const uint32_t t = tsize[-s];
+        const uint32_t x = first_at_least(pw + toff[-s], 0, t, next);
+        if (x < t && pw[toff[-s] + x] < best) best = pw[toff[-s] + x];
+      }
+    }
+    if (best == 0xffffffffu) break;
+    uint32_t cnt = 0;
+    for (int64_t j = 0; j < k; ++j) {
+      const int32_t s = g.sym[a + j];
+      if (s >= 0) {
+        cnt += (uint32_t)s == best;
+      } else {
+        const uint32_t t = tsize[-s];
+        const uint32_t x = first_at_least(pw + toff[-s], 0, t, best);
+        if (x < t && pw[toff[-s] + x] == best) cnt += pc[toff[-s] + x];
+      }
+    }
+    pw[out + m] = best;
+    pc[out + m] = cnt;
+    ++m;
+    next = best + 1;
   }
   tsize[r] = m;
 }
 
+__global__ __launch_bounds__(kTvBigThreads) void k_tv_merge_big(DevGrammar g, const int32_t* list,
+                                                                const int32_t* count, const uint64_t* toff,
+                                                                uint32_t* tsize, uint32_t* pw, uint32_t* pc) {
+  __shared__ uint32_t cnt[kWcBucket];
+  __shared__ uint32_t cur[kTvBigPieces], endp[kTvBigPieces], pref[kTvBigPieces];
+  __shared__ uint32_t red[16];
+  const int32_t nr = *count;
+  for (int32_t j = blockIdx.x; j < nr; j += gridDim.x) {
+    const int32_t r = list[j];
+    const int64_t a = g.rule_off[r];
+    const int32_t k = (int32_t)(g.rule_off[r + 1] - a);
+    if (k > kTvBigPieces) {
+      if (threadIdx.x == 0) tv_merge_serial(g, r, toff, tsize, pw, pc);
+      __syncthreads();
+      continue;
+    }
+    const uint64_t out = toff[r];
+    for (int p = threadIdx.x; p < k; p += blockDim.x) cur[p] = 0;
+    for (int x = threadIdx.x; x < kWcBucket; x += blockDim.x) cnt[x] = 0;
+    __syncthreads();
+    uint32_t m = 0;
+    while (true) {
+      // the window is the 4096-id bucket of the smallest pending word
+      uint32_t lmin = 0xffffffffu;
+      for (int p = threadIdx.x; p < k; p += blockDim.x) {
+        const int32_t s = g.sym[a + p];
+        uint32_t wd = 0xffffffffu;
+        if (s >= 0) {
+          if (cur[p] == 0) wd = (uint32_t)s;
+        } else if (cur[p] < tsize[-s]) {
+          wd = pw[toff[-s] + cur[p]];
+        }
+        lmin = wd < lmin ? wd : lmin;
+      }
+      const uint32_t w0 = block_min_1024(lmin, red);
+      if (w0 == 0xffffffffu) break;
+      const uint32_t wb = w0 & ~(uint32_t)(kWcBucket - 1);
+      const uint64_t w1 = (uint64_t)wb + kWcBucket;
+      // every piece's inputs inside the window, and their offsets (4 pieces per thread)
+      uint32_t mine[4], tot4 = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int p = threadIdx.x * 4 + x;
+        uint32_t c = 0;
+        if (p < k) {
+          const int32_t s = g.sym[a + p];
+          uint32_t e;
+          if (s >= 0) {
+            e = (cur[p] == 0 && (uint64_t)s < w1) ? 1u : cur[p];
+          } else {
+            const uint32_t t = tsize[-s];
+            e = w1 > 0xffffffffull ? t : first_at_least(pw + toff[-s], cur[p], t, (uint32_t)w1);
+          }
+          endp[p] = e;
+          c = e - cur[p];
+        }
+        mine[x] = c;
+        tot4 += c;
+      }
+      uint32_t total;
+      uint32_t base = block_scan_1024(tot4, red, &total);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int p = threadIdx.x * 4 + x;
+        if (p < k) pref[p] = base;
+        base += mine[x];
+      }
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+        int lo = 0, hi = k - 1;  // last piece with pref <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pref[mid] <= e) lo = mid;
+          else hi = mid - 1;
+        }
+        const int32_t s = g.sym[a + lo];
+        if (s >= 0) {
+          atomicAdd(&cnt[(uint32_t)s - wb], 1u);
+        } else {
+          const uint64_t at = toff[-s] + cur[lo] + (e - pref[lo]);
+          atomicAdd(&cnt[pw[at] - wb], pc[at]);
+        }
+      }
+      __syncthreads();
+      // the window's nonzero slots, in word order (4 consecutive slots per thread)
+      uint32_t c4[4], nz = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) c4[x] = cnt[threadIdx.x * 4 + x], nz += c4[x] != 0;
+      uint32_t nz_total;
+      uint32_t pos = m + block_scan_1024(nz, red, &nz_total);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        if (c4[x]) {
+          pw[out + pos] = wb + threadIdx.x * 4 + x;
+          pc[out + pos] = c4[x];
+          ++pos;
+          cnt[threadIdx.x * 4 + x] = 0;
+        }
+      }
+      m += nz_total;
+      for (int p = threadIdx.x; p < k; p += blockDim.x) cur[p] = endp[p];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tsize[r] = m;
+    __syncthreads();
+  }
+}
+
 hipError_t launch_tv_tables(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, const uint64_t* toff,
-                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, hipStream_t s) {
+                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, int32_t* list_wave, int32_t* list_big,
+                            int32_t* counts, hipStream_t s) {
+  hipError_t e = launch_fill_i32(counts, 2 * ((int64_t)depth + 2), 0, s);
+  if (e != hipSuccess) return e;
   for (int32_t d = depth; d >= 1; --d) {
     const int32_t lo = level_off_host[d], hi = level_off_host[d + 1];
     if (hi <= lo) continue;
-    k_tv_merge_level<<<(unsigned)((hi - lo + 63) / 64), 64, 0, s>>>(g, g.level_rule + lo, hi - lo, toff, tsize, pw, pc);
-    hipError_t e = hipGetLastError();
+    const int32_t n = hi - lo;
+    int32_t* c = counts + 2 * d;
+    k_tv_classify<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, n, tsize, list_wave, list_big, c);
+    const int32_t gw = (n + kTvWaveWaves - 1) / kTvWaveWaves;
+    k_tv_merge_wave<<<(unsigned)(gw < 4096 ? gw : 4096), 64 * kTvWaveWaves, 0, s>>>(g, list_wave, c, toff, tsize, pw, pc);
+    k_tv_merge_big<<<(unsigned)(n < 1024 ? n : 1024), kTvBigThreads, 0, s>>>(g, list_big, c + 1, toff, tsize, pw, pc);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

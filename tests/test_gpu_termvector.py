@@ -100,6 +100,25 @@ def test_long_bodies_and_empty_files(ctx):
     check(ctx, g)
 
 
+def test_large_tables(ctx):
+    """Merges spread over a workgroup: a rule whose children's tables hold
+    thousands of words (more inputs than one wave merges), overlapping word
+    ranges that span several 4096-id windows, repeated children, and a rule
+    with more body symbols than the workgroup merge keeps cursors for."""
+    rng = np.random.default_rng(11)
+    V = 20000
+    a = rng.permutation(V)[:3000].astype(np.int32)                   # R1: 3000 distinct words
+    b = np.concatenate([a[1000:2500], rng.integers(0, V, 1500)]).astype(np.int32)  # R2: overlaps R1
+    c = np.array([-1, -2, 7, -1, 19999, 0], np.int32)               # R3: R1 twice, R2, words
+    d = rng.integers(0, V, 5000).astype(np.int32)                    # R4: 5000 symbols
+    e = np.array([-3, -4, 5], np.int32)                              # R5
+    root = np.array([-5, 3, -3, -4, -5, -1, -2, 12], np.int32)
+    bodies = [root, a, b, c, d, e]
+    rule_off = np.cumsum([0] + [len(x) for x in bodies]).astype(np.int64)
+    g = synth.Grammar(rule_off, np.concatenate(bodies), np.array([0, 3, 3, 8], np.int64), V)
+    check(ctx, g)
+
+
 def test_tv_recipe_scaled(ctx):
     c, g = synth.workload("tv-4000files", scale=0.01)  # 40 files
     check(ctx, g, brute=False)
