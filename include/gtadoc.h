@@ -154,6 +154,13 @@ int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream);
  * Errors: INVALID_ARG, OOM, HIP. */
 int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream);
 
+/* Inverted index from a term vector result `term_vector` of the same grammar
+ * (from gtadoc_term_vector on g, not yet freed): the same output as
+ * gtadoc_inverted_index without recomputing the term vector. Synchronizes
+ * `stream`. Errors: INVALID_ARG (null, or a result that is not a term vector
+ * of g), OOM, HIP. */
+int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out, void* stream);
+
 /* Sequence count (Section "Sequence Support"): occurrences of every run of n
  * consecutive words inside one file (runs never cross files), n in {2, 3}.
  * Result arrays: [0] uint64 key[U] ascending, [1] uint64 count[U], where the

@@ -155,6 +155,7 @@ struct gtadoc_result_s {
     int eb;
   } a[4]{};
   int na = 0;
+  const gtadoc_grammar_s* tv_of = nullptr;  // set on a term vector result: its grammar
 };
 
 namespace {
@@ -729,19 +730,15 @@ int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
   res->a[1] = {a.word, a.nnz, 4};
   res->a[2] = {a.cnt, a.nnz, 8};
   res->na = 3;
+  res->tv_of = g;
   *out = res;
   return GTADOC_OK;
 }
 
-int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
-  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
-  Call call(g->ctx, stream);
-  int rc = call.begin();
-  if (rc) return rc;
+namespace {
+// Inverted index of g from its term vector `a`, into a new result.
+int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, gtadoc_result* out) {
   hipStream_t s = call.stream();
-  TvArrays a;
-  rc = term_vector_into(g, call, nullptr, &a);
-  if (rc) return rc;
   const int64_t NNZ = a.nnz;
   const int32_t V = g->d.V;
   gtadoc_result res = new_result(g->ctx);
@@ -777,8 +774,32 @@ int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
   *out = res;
   return GTADOC_OK;
 }
+}  // namespace
 
+int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  TvArrays a;
+  rc = term_vector_into(g, call, nullptr, &a);
+  if (rc) return rc;
+  return inverted_index_from(g, call, a, out);
+}
 
+int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out, void* stream) {
+  if (!g || !term_vector || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (term_vector->tv_of != g) return fail(GTADOC_ERR_INVALID_ARG, "not a term vector result of this grammar");
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  TvArrays a;
+  a.off = static_cast<int64_t*>(term_vector->a[0].p);
+  a.word = static_cast<uint32_t*>(term_vector->a[1].p);
+  a.cnt = static_cast<uint64_t*>(term_vector->a[2].p);
+  a.nnz = term_vector->a[1].n;
+  return inverted_index_from(g, call, a, out);
+}
 
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");

@@ -99,9 +99,9 @@ __global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t
                                                      const uint32_t* tsize, int32_t* list_wave, int32_t* list_big,
                                                      int32_t* counts) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t r = rules[i];
-  const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  const bool live = i < n;
+  const int32_t r = live ? rules[i] : 0;
+  const int64_t a = live ? g.rule_off[r] : 0, b = live ? g.rule_off[r + 1] : 0;
   uint64_t n_in = 0;
   for (int64_t q0 = a; q0 < b; q0 += 8) {
     int32_t v[8];
@@ -111,8 +111,13 @@ __global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t
     for (int k = 0; k < 8; ++k)
       if (q0 + k < b) n_in += v[k] >= 0 ? 1u : tsize[-v[k]];
   }
-  if (n_in <= (uint64_t)kTvWaveMax) list_wave[atomicAdd(&counts[0], 1)] = r;
-  else list_big[atomicAdd(&counts[1], 1)] = r;
+  // one counter atomic per wave and list (a per-thread atomic on one address
+  // serializes millions of them)
+  const bool small = n_in <= (uint64_t)kTvWaveMax;
+  const int32_t at_w = wave_append(live && small, &counts[0]);
+  const int32_t at_b = wave_append(live && !small, &counts[1]);
+  if (live && small) list_wave[at_w] = r;
+  if (live && !small) list_big[at_b] = r;
 }
 
 __global__ __launch_bounds__(64 * kTvWaveWaves) void k_tv_merge_wave(DevGrammar g, const int32_t* list,
@@ -425,10 +430,18 @@ __device__ __forceinline__ int64_t file_of_unit(const int64_t* unit_off, int64_t
   return lo;
 }
 
-// Pass 1 (count) and pass 2 (scatter) walk the same inputs of one unit.
+// Pass 1 (count) and pass 2 (scatter) walk the same inputs of one unit: its
+// root words (count 1) and every entry of the table of each referenced
+// child. The unit's inputs are numbered by an exclusive scan of the symbols'
+// input counts, and the workgroup's threads take them in turn (a binary
+// search in LDS finds the symbol of input e), so a child with a huge table
+// is spread over the whole workgroup instead of one thread.
 template <bool kScatter>
 __global__ __launch_bounds__(256) void k_tv_group(DevGrammar g, TvFiles t, uint64_t* entries) {
   extern __shared__ uint32_t lds_tv[];  // per-bucket counts (pass 1) or cursors (pass 2)
+  __shared__ uint32_t pre[kTileSyms];   // exclusive prefix of the symbols' input counts
+  __shared__ int32_t syms[kTileSyms];
+  __shared__ uint32_t part[4];
   __shared__ int64_t sh_f;
   const int64_t u = blockIdx.x;
   if (threadIdx.x == 0) sh_f = file_of_unit(t.unit_off, g.F, u);
@@ -438,23 +451,48 @@ __global__ __launch_bounds__(256) void k_tv_group(DevGrammar g, TvFiles t, uint6
   const int64_t k = u - t.unit_off[f];
   const int64_t slot0 = (int64_t)t.nb * t.unit_off[f] + k;
   for (int b = threadIdx.x; b < t.nb; b += blockDim.x) lds_tv[b] = kScatter ? t.table[slot0 + b * n_f] : 0u;
-  __syncthreads();
   const int64_t fs = g.file_off[f] + k * kTileSyms, fe0 = g.file_off[f + 1];
-  const int64_t fe = fs + kTileSyms < fe0 ? fs + kTileSyms : fe0;
-  for (int64_t q = fs + threadIdx.x * kPerThread, qe = q + kPerThread; q < qe && q < fe; ++q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      const uint32_t at = atomicAdd(&lds_tv[s >> kWcBits], 1u);
-      if (kScatter) entries[at] = (1ull << kWcBits) | (uint64_t)(s & (kWcBucket - 1));
-    } else {
-      const uint64_t o = t.toff[-s];
-      const uint32_t n = t.tsize[-s];
-      for (uint32_t e = 0; e < n; ++e) {
-        const uint32_t wd = t.pw[o + e];
-        const uint32_t at = atomicAdd(&lds_tv[wd >> kWcBits], 1u);
-        if (kScatter) entries[at] = ((uint64_t)t.pc[o + e] << kWcBits) | (uint64_t)(wd & (kWcBucket - 1));
-      }
+  const int32_t len = (int32_t)(fs + kTileSyms < fe0 ? kTileSyms : fe0 - fs);
+  // input counts of this thread's 16 symbols, then their offsets
+  uint32_t c[kPerThread], mine = 0;
+#pragma unroll
+  for (int x = 0; x < kPerThread; ++x) {
+    const int32_t j = threadIdx.x * kPerThread + x;
+    int32_t sv = 0;
+    c[x] = 0;
+    if (j < len) {
+      sv = g.sym[fs + j];
+      c[x] = sv >= 0 ? 1u : t.tsize[-sv];
+      syms[j] = sv;
     }
+    mine += c[x];
+  }
+  uint32_t total;
+  uint32_t base = block_exclusive_scan_256(mine, part, &total);
+#pragma unroll
+  for (int x = 0; x < kPerThread; ++x) {
+    const int32_t j = threadIdx.x * kPerThread + x;
+    if (j < len) pre[j] = base;
+    base += c[x];
+  }
+  __syncthreads();
+  for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    int32_t lo = 0, hi = len - 1;  // last symbol with pre <= e (every symbol has >= 1 input)
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    const int32_t sv = syms[lo];
+    uint32_t wd, cn;
+    if (sv >= 0) {
+      wd = (uint32_t)sv, cn = 1;
+    } else {
+      const uint64_t at = t.toff[-sv] + (e - pre[lo]);
+      wd = t.pw[at], cn = t.pc[at];
+    }
+    const uint32_t at = atomicAdd(&lds_tv[wd >> kWcBits], 1u);
+    if (kScatter) entries[at] = ((uint64_t)cn << kWcBits) | (uint64_t)(wd & (kWcBucket - 1));
   }
   if (!kScatter) {
     __syncthreads();

@@ -56,6 +56,7 @@ EXPORTS = {
     "gtadoc_sort": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gtadoc_term_vector": [_vp, _vp, _vp],
     "gtadoc_inverted_index": [_vp, _vp, _vp],
+    "gtadoc_inverted_index_from_tv": [_vp, _vp, _vp, _vp],
     "gtadoc_sequence_count": [_vp, _int, _vp, _vp],
     "gtadoc_result_array": [_vp, _int, _vp, _vp, _vp],
     "gtadoc_result_free": [_vp],
@@ -253,6 +254,10 @@ class Grammar:
 
     def inverted_index(self, stream=None) -> Result:
         return self._result(lib().gtadoc_inverted_index, stream=stream)
+
+    def inverted_index_from(self, term_vector: "Result", stream=None) -> Result:
+        """Inverted index from this grammar's term vector result (no recomputation)."""
+        return self._result(lib().gtadoc_inverted_index_from_tv, term_vector.handle, stream=stream)
 
     def sequence_count(self, n: int, stream=None) -> Result:
         return self._result(lib().gtadoc_sequence_count, n, stream=stream)

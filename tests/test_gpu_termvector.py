@@ -55,6 +55,13 @@ def check(ctx, g, brute=True):
         ioff, ifile = gpu_ii(G)
         woff2, wfile = oracle.inverted_index(woff, wword, g.vocab)
         assert np.array_equal(ioff, woff2) and np.array_equal(ifile, wfile)
+        # the same from a term vector result, without recomputing it
+        tv = G.term_vector()
+        ii = G.inverted_index_from(tv)
+        assert np.array_equal(ii.arrays[0].cpu().numpy(), woff2)
+        assert np.array_equal(ii.arrays[1].cpu().numpy().view(np.uint32), wfile)
+        ii.free()
+        tv.free()
     finally:
         G.free()
 
@@ -127,3 +134,24 @@ def test_tv_recipe_scaled(ctx):
 def test_wc_recipe_single_file(ctx):
     c, g = synth.workload("wc-200k")
     check(ctx, g)
+
+
+def test_inverted_index_from_foreign_result(ctx):
+    import paper_2106_06889_amd as gt
+    c = synth.random_corpus(5, 3, 400, 30)
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    G, H = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab), ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        sc = G.sequence_count(2)
+        with pytest.raises(gt.GtadocError) as e:
+            G.inverted_index_from(sc)
+        assert e.value.code == gt.ERR_INVALID_ARG
+        tv = H.term_vector()
+        with pytest.raises(gt.GtadocError) as e:
+            G.inverted_index_from(tv)  # a term vector of another grammar
+        assert e.value.code == gt.ERR_INVALID_ARG
+        tv.free()
+        sc.free()
+    finally:
+        G.free()
+        H.free()
