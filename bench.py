@@ -87,6 +87,32 @@ def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
             "sample": f"whole grammar, {reps} run(s) of the sequential traversal {what}, {per:.3f} s each"}
 
 
+PHASE_KERNEL = {"levels": "k_levels"}
+
+
+def measured_traffic(phase: str, workload: str):
+    """HBM bytes per launch of the phase's kernel from a committed PMC
+    summary (profiles/*_hbm_traffic.md), or None when there is none for this
+    workload or the kernel's source has changed since the counters were
+    taken."""
+    import glob
+    import hashlib
+    kernel = PHASE_KERNEL.get(phase)
+    if not kernel:
+        return None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record: "):
+                continue
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("kernel") != kernel or rec.get("workload") != workload:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["source_sha256"]:
+                return int(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def roofline(name: str, nbytes: float, us: float) -> dict:
     achieved = nbytes / (us * 1e-6) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -219,6 +245,8 @@ def run_query(args):
                                 4 * S + 8 * (R + 1) + 8 * (F + 1) + 12 * sizes.get("nnz_tv", 0))
     dom = max((p for p in cands if p in phases), key=lambda p: phases[p]["avg_us"] * phases[p]["count"])
     roof = roofline(cands[dom][0], cands[dom][1], phases[dom]["avg_us"])
+    if args.scale == 1.0:
+        roof["traffic"] = measured_traffic(dom, args.workload)
     others = {p: roofline(cands[p][0], cands[p][1], phases[p]["avg_us"]) for p in cands if p in phases and p != dom}
 
     cpu = None
