@@ -214,7 +214,7 @@ int gtadoc_batch_create(gtadoc_ctx ctx, int max_items, uint64_t max_entries, gta
 /* Word count of gs[i] into counts[i] (device arrays of vocab_i uint64), for
  * i < n, asynchronous on `stream`. Waits for the plan's previous batch
  * before reusing its descriptors. Every grammar must belong to the plan's
- * context and use the bucketed word count (vocab <= 2^24, tokens < 2^52).
+ * context and use the bucketed word count (vocab <= 2^24).
  * Errors: INVALID_ARG (n, sizes, foreign grammar), UNSUPPORTED, HIP. */
 int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* const* counts, int n, void* stream);
 

@@ -123,7 +123,7 @@ struct gtadoc_batch_s {
   std::vector<Block> blocks;
   gt::BatchDesc* host = nullptr;   // pinned staging
   gt::BatchDesc* dev = nullptr;    // in the arena
-  uint64_t* entries = nullptr;     // scratch in the arena
+  uint32_t* entries = nullptr;     // scratch in the arena
   int max_items = 0;
   uint64_t max_entries = 0;
   hipEvent_t done = nullptr;
@@ -520,9 +520,9 @@ int word_count_into(gtadoc_grammar g, Call& call, uint64_t* counts) {
     HIP_TRY(gt::launch_fill_u64(counts, d.V, 0, s));
     return GTADOC_OK;
   }
-  if (d.wc_nb > 0 && (uint64_t)g->st.tokens < (1ull << (64 - gt::kWcBits))) {
-    uint64_t* entries = call.scratch<uint64_t>(W);
-    if (!entries) return oom("word entries", 8ull * W);
+  if (d.wc_nb > 0) {
+    uint32_t* entries = call.scratch<uint32_t>(W);
+    if (!entries) return oom("word entries", 4ull * W);
     PhaseScope t(g->ctx, GTADOC_PHASE_WORD_COUNT, s);
     HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, g->ctx->wc_chunk, s));
     t.end();
@@ -950,13 +950,13 @@ int gtadoc_batch_create(gtadoc_ctx ctx, int max_items, uint64_t max_entries, gta
   }
   b->blocks.push_back(blk);
   b->dev = reinterpret_cast<gt::BatchDesc*>(ctx->base + blk.off);
-  if (!ctx->arena.alloc(std::max<uint64_t>(max_entries, 1) * 8, &blk)) {
+  if (!ctx->arena.alloc(std::max<uint64_t>(max_entries, 1) * 4, &blk)) {
     release_all(ctx, b->blocks);
     delete b;
-    return oom("batch entries", 8 * max_entries);
+    return oom("batch entries", 4 * max_entries);
   }
   b->blocks.push_back(blk);
-  b->entries = reinterpret_cast<uint64_t*>(ctx->base + blk.off);
+  b->entries = reinterpret_cast<uint32_t*>(ctx->base + blk.off);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->host), sizeof(gt::BatchDesc), hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     if (b->host) (void)hipHostFree(b->host);
@@ -996,7 +996,7 @@ int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* 
   for (int i = 0; i < n; ++i) {
     const gtadoc_grammar g = gs[i];
     if (!g || g->ctx != ctx || !counts[i]) return fail(GTADOC_ERR_INVALID_ARG, "item %d: null or foreign grammar", i);
-    if (g->d.wc_nb == 0 || (uint64_t)g->st.tokens >= (1ull << (64 - gt::kWcBits)))
+    if (g->d.wc_nb == 0)
       return fail(GTADOC_ERR_UNSUPPORTED, "item %d: grammar needs the direct word count", i);
     const int64_t W = g->st.word_syms;
     gt::BatchItem& it = h.items[i];

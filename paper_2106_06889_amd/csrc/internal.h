@@ -128,14 +128,14 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_
 
 // word count and sort
 hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics
-hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint64_t* entries, int64_t W,
+hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint32_t* entries, int64_t W,
                                      int64_t chunk, hipStream_t s);
 // batched word count: descriptors in device memory
 constexpr int kBatchMax = 1024;
 struct BatchItem {
   DevGrammar g;
   uint64_t* out;       // [V] counts
-  uint64_t* entries;   // [W] scratch
+  uint32_t* entries;   // [W] scratch
   int64_t W;
 };
 struct BatchDesc {

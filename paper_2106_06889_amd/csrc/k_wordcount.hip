@@ -47,45 +47,127 @@ __global__ __launch_bounds__(kTileThreads) void k_word_count(DevGrammar g, uint6
   }
 }
 
-// Scatter of block `blk` (kSubTiles tiles). LDS holds the block's write
-// cursor per bucket, starting at its offset from the load-time scan.
-__device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t blk, uint64_t* entries, int32_t* roff,
-                                                 uint32_t* cursor) {
+// Scatter of block `blk` (kSubTiles tiles of kTileSyms symbols, walked one
+// after the other by kWcScatterThreads threads, 4 symbols each). Entries are
+// 32-bit: weight << 12 | low 12 bits of the word id, for weights below 2^20;
+// a word of a heavier rule (rare: a rule used a million times) adds its
+// weight to the count directly and leaves a zero-weight entry. The block's
+// entries are staged in LDS grouped by bucket (local offsets from the
+// block's bucket counts, known from the load-time histogram), then every
+// bucket run is copied to its global position by consecutive lanes, so the
+// writes are whole lines instead of one 8-byte store per word.
+constexpr int kWcScatterThreads = 1024;
+constexpr int kWcSymsPerThread = kTileSyms / kWcScatterThreads;  // 4: one 16-byte load
+constexpr uint64_t kWcMaxWeight = 1ull << (32 - kWcBits);
+
+struct WcScatterLds {
+  int32_t roff[kTileRuleSlots];
+  uint32_t stage[kBlockSyms];
+};
+
+// Dynamic LDS after WcScatterLds: cur[nb], lstart[nb], gstart[nb] (uint32).
+__device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t blk, uint32_t* entries, uint64_t* counts,
+                                                 WcScatterLds& L, uint32_t* dyn, int64_t W) {
+  const int nb = g.wc_nb;
+  uint32_t* cur = dyn;
+  uint32_t* lstart = dyn + nb;
+  uint32_t* gstart = dyn + 2 * nb;
+  __shared__ uint32_t red[16];
   const int64_t slot = xcd_slot(blk, g.nslot);
-  for (int b = threadIdx.x; b < g.wc_nb; b += blockDim.x) cursor[b] = g.wc_off[(int64_t)b * g.nslot + slot];
+  // the block's bucket counts: differences of consecutive offsets (next slot, or next bucket row)
+  uint32_t mine[4], tot4 = 0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int b = threadIdx.x * 4 + x;
+    uint32_t c = 0;
+    if (b < nb) {
+      const int64_t at = (int64_t)b * g.nslot + slot;
+      const uint32_t o = g.wc_off[at];
+      const int64_t nxt = slot + 1 < g.nslot ? (int64_t)g.wc_off[at + 1]
+                                             : (b + 1 < nb ? (int64_t)g.wc_off[(int64_t)(b + 1) * g.nslot] : W);
+      c = (uint32_t)(nxt - o);
+      gstart[b] = o;
+    }
+    mine[x] = c;
+    tot4 += c;
+  }
+  // exclusive scan of the counts over the 1024 threads (16 waves)
+  uint32_t x_incl = tot4;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x_incl, o);
+    if (lane_id() >= o) x_incl += y;
+  }
+  if (lane_id() == 63) red[threadIdx.x >> 6] = x_incl;
+  __syncthreads();
+  uint32_t base = 0, n_block = 0;
+#pragma unroll
+  for (int w = 0; w < kWcScatterThreads / 64; ++w) {
+    if (w < (int)(threadIdx.x >> 6)) base += red[w];
+    n_block += red[w];
+  }
+  base += x_incl - tot4;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int b = threadIdx.x * 4 + x;
+    if (b < nb) lstart[b] = base, cur[b] = base;
+    base += mine[x];
+  }
+  __syncthreads();
   for (int sub = 0; sub < kSubTiles; ++sub) {
     const int64_t tile = blk * kSubTiles + sub;
     if (tile >= g.ntiles) break;  // uniform for the block
-    const Tile t = tile_begin(g, tile, roff);
-    const int32_t q0 = threadIdx.x * kPerThread;
+    const Tile t = tile_begin(g, tile, L.roff);
+    const int32_t q0 = threadIdx.x * kWcSymsPerThread;
     if (q0 < t.len) {
-      int32_t v[kPerThread];
-      tile_load_syms(g, t, q0, v);
-      int32_t j = tile_find(roff, t.nr, q0);
-      int32_t next = roff[j + 1];
+      int32_t v[kWcSymsPerThread];
+      if (q0 + kWcSymsPerThread <= t.len) {
+        const v4i32 x4 = __builtin_nontemporal_load(reinterpret_cast<const v4i32*>(g.sym + t.a + q0));
+        v[0] = x4.x, v[1] = x4.y, v[2] = x4.z, v[3] = x4.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < kWcSymsPerThread; ++k) v[k] = q0 + k < t.len ? g.sym[t.a + q0 + k] : 0;
+      }
+      int32_t j = tile_find(L.roff, t.nr, q0);
+      int32_t next = L.roff[j + 1];
       uint64_t wr = g.w[t.r0 + j];
 #pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
+      for (int k = 0; k < kWcSymsPerThread; ++k) {
         const int32_t q = q0 + k;
         if (q >= t.len) continue;
         if (q >= next) {
-          while (q >= next) next = roff[++j + 1];
+          while (q >= next) next = L.roff[++j + 1];
           wr = g.w[t.r0 + j];
         }
         const int32_t s = v[k];
         if (s >= 0) {
-          const uint32_t at = atomicAdd(&cursor[s >> kWcBits], 1u);
-          entries[at] = (wr << kWcBits) | (uint64_t)(s & (kWcBucket - 1));
+          const uint32_t at = atomicAdd(&cur[s >> kWcBits], 1u);
+          const bool light = wr < kWcMaxWeight;
+          L.stage[at] = (light ? (uint32_t)(wr << kWcBits) : 0u) | (uint32_t)(s & (kWcBucket - 1));
+          if (!light) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[s]), (unsigned long long)wr);
         }
       }
     }
-    __syncthreads();  // roff (and the cursors, for the next block) are rewritten
+    __syncthreads();  // roff is rewritten by the next tile
   }
+  // copy out: the run of bucket b goes to gstart[b] .. ; lanes take consecutive entries
+  for (uint32_t e = threadIdx.x; e < n_block; e += blockDim.x) {
+    int lo = 0, hi = nb - 1;  // last bucket with lstart <= e (empty buckets share the next start)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lstart[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    entries[gstart[lo] + (e - lstart[lo])] = L.stage[e];
+  }
+  __syncthreads();  // LDS is reused by the next block of a persistent grid
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_wc_scatter(DevGrammar g, uint64_t* entries) {
-  extern __shared__ int32_t lds_wc[];
-  wc_scatter_block(g, blockIdx.x, entries, lds_wc, reinterpret_cast<uint32_t*>(lds_wc + kTileRuleSlots));
+__global__ __launch_bounds__(kWcScatterThreads) void k_wc_scatter(DevGrammar g, uint32_t* entries, uint64_t* counts,
+                                                                  int64_t W) {
+  __shared__ WcScatterLds L;
+  extern __shared__ uint32_t lds_wc[];
+  wc_scatter_block(g, blockIdx.x, entries, counts, L, lds_wc, W);
 }
 
 // Reduce: the entry array is cut into chunks (bucket sizes follow the word
@@ -115,7 +197,7 @@ struct WcReduceLds {
   int first_bucket;
 };
 
-__device__ __forceinline__ void wc_reduce_chunk(const DevGrammar& g, const uint64_t* entries, int64_t W,
+__device__ __forceinline__ void wc_reduce_chunk(const DevGrammar& g, const uint32_t* entries, int64_t W,
                                                 uint64_t* counts, int64_t chunk_idx, int64_t chunk, WcReduceLds& L) {
   const int64_t c_lo = chunk_idx * chunk;
   const int64_t c_hi = c_lo + chunk < W ? c_lo + chunk : W;
@@ -128,8 +210,9 @@ __device__ __forceinline__ void wc_reduce_chunk(const DevGrammar& g, const uint6
     if (b_lo >= c_hi) break;
     const int64_t lo = b_lo > c_lo ? b_lo : c_lo, hi = b_hi < c_hi ? b_hi : c_hi;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      const uint64_t e = __builtin_nontemporal_load(entries + i);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&mine[e & (kWcBucket - 1)]), (unsigned long long)(e >> kWcBits));
+      const uint32_t e = __builtin_nontemporal_load(entries + i);
+      if (e >> kWcBits)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&mine[e & (kWcBucket - 1)]), (unsigned long long)(e >> kWcBits));
     }
     __syncthreads();
     const int64_t base = (int64_t)b * kWcBucket;
@@ -144,7 +227,7 @@ __device__ __forceinline__ void wc_reduce_chunk(const DevGrammar& g, const uint6
   }
 }
 
-__global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const uint64_t* entries, int64_t W,
+__global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const uint32_t* entries, int64_t W,
                                                           uint64_t* counts, int64_t chunk) {
   __shared__ WcReduceLds L;
   for (int i = threadIdx.x; i < kWcCopies * kWcBucket; i += blockDim.x) (&L.acc[0][0])[i] = 0;
@@ -152,13 +235,12 @@ __global__ __launch_bounds__(kWcThreads) void k_wc_reduce(DevGrammar g, const ui
   wc_reduce_chunk(g, entries, W, counts, blockIdx.x, chunk, L);
 }
 
-hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint64_t* entries, int64_t W,
+hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint32_t* entries, int64_t W,
                                      int64_t chunk, hipStream_t s) {
   hipError_t e = launch_fill_u64(counts, g.V, 0, s);
   if (e != hipSuccess) return e;
   if (g.ntiles == 0 || W == 0) return hipSuccess;
-  const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.wc_nb);
-  k_wc_scatter<<<(unsigned)g.nblk, kTileThreads, shmem, s>>>(g, entries);
+  k_wc_scatter<<<(unsigned)g.nblk, kWcScatterThreads, sizeof(uint32_t) * 3 * g.wc_nb, s>>>(g, entries, counts, W);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_wc_reduce<<<(unsigned)((W + chunk - 1) / chunk), kWcThreads, 0, s>>>(g, entries, W, counts, chunk);
@@ -193,15 +275,15 @@ __global__ __launch_bounds__(256) void k_wcb_fill(const BatchDesc* d) {
   }
 }
 
-__global__ __launch_bounds__(kTileThreads) void k_wcb_scatter(const BatchDesc* d) {
-  extern __shared__ int32_t lds_wcb[];
+__global__ __launch_bounds__(kWcScatterThreads) void k_wcb_scatter(const BatchDesc* d) {
+  __shared__ WcScatterLds L;
+  extern __shared__ uint32_t lds_wcb[];
   const int n = d->n;
   const int64_t total = d->scatter_base[n];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int i = batch_item_owner(d->scatter_base, n, it);
     const BatchItem& b = d->items[i];
-    wc_scatter_block(b.g, it - d->scatter_base[i], b.entries, lds_wcb,
-                     reinterpret_cast<uint32_t*>(lds_wcb + kTileRuleSlots));
+    wc_scatter_block(b.g, it - d->scatter_base[i], b.entries, b.out, L, lds_wcb, b.W);
   }
 }
 
@@ -223,7 +305,7 @@ hipError_t launch_word_count_batch(const BatchDesc* d, int grid_scatter, int gri
   k_wcb_fill<<<grid_scatter, 256, 0, s>>>(d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_wcb_scatter<<<grid_scatter, kTileThreads, sizeof(int32_t) * (kTileRuleSlots + max_nb), s>>>(d);
+  k_wcb_scatter<<<grid_scatter, kWcScatterThreads, sizeof(uint32_t) * 3 * max_nb, s>>>(d);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_wcb_reduce<<<grid_reduce, kWcThreads, 0, s>>>(d);
