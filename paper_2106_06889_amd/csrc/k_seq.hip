@@ -173,62 +173,101 @@ __device__ __forceinline__ Piece piece_tail(const DevGrammar& g, const uint64_t*
   return p;
 }
 
+// Two-level exact table: every workgroup first merges its windows in an LDS
+// open-addressing table (key -> weight sum); a key that finds no slot within
+// kSeqProbes probes goes straight to the global table, and at the end the
+// LDS slots are flushed to the global table, one insert-or-add per distinct
+// key of the tile instead of one per window.
+constexpr int kSeqSlots = 2048;
+constexpr int kSeqProbes = 8;
+
+struct SeqLds {
+  int32_t roff[kTileRuleSlots];
+  uint64_t key[kSeqSlots];
+  uint64_t val[kSeqSlots];
+};
+
+__device__ __forceinline__ void seq_add(SeqLds& L, uint64_t* keys, uint64_t* vals, uint64_t mask, uint64_t key,
+                                        uint64_t w, uint32_t* overflow) {
+  const uint32_t h = (uint32_t)(mix64(key) >> 40) & (kSeqSlots - 1);
+#pragma unroll
+  for (int p = 0; p < kSeqProbes; ++p) {
+    const uint32_t slot = (h + p) & (kSeqSlots - 1);
+    uint64_t k = __hip_atomic_load(&L.key[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == kEmptyKey)
+      k = atomicCAS(reinterpret_cast<unsigned long long*>(&L.key[slot]), (unsigned long long)kEmptyKey,
+                    (unsigned long long)key);
+    if (k == kEmptyKey || k == key) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(&L.val[slot]), (unsigned long long)w);
+      return;
+    }
+  }
+  table_add(keys, vals, mask, key, w, overflow);
+}
+
 // Owned windows, position-parallel over the tiles of all bodies. The root is
 // split at file boundaries: windows never cross files.
 __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int n, const uint64_t* len,
                                                               const int32_t* head, const int32_t* tail, uint64_t* keys,
                                                               uint64_t* vals, uint64_t mask, uint32_t* overflow) {
-  __shared__ int32_t roff[kTileRuleSlots];
-  const Tile t = tile_begin(g, blockIdx.x, roff);
+  __shared__ SeqLds L;
+  for (int x = threadIdx.x; x < kSeqSlots; x += blockDim.x) L.key[x] = kEmptyKey, L.val[x] = 0;
+  const Tile t = tile_begin(g, blockIdx.x, L.roff);  // (synchronizes)
   const int32_t q0 = threadIdx.x * kPerThread;
-  if (q0 >= t.len) return;
-  int32_t j = tile_find(roff, t.nr, q0);
-  int32_t next = roff[j + 1];
-  int64_t f = -1, f_end = 0;  // file span of the current root position
-  for (int k = 0; k < kPerThread; ++k) {
-    const int32_t qt = q0 + k;
-    if (qt >= t.len) break;
-    while (qt >= next) next = roff[++j + 1];
-    const int32_t r = t.r0 + j;
-    const int64_t q = t.a + qt;
-    int64_t end;
-    uint64_t wt;
-    if (r == 0) {
-      if (q >= f_end) {  // locate the file span holding q (binary search on file_off)
-        int64_t lo = 0, hi = g.F - 1;
-        while (lo < hi) {
-          const int64_t mid = (lo + hi + 1) >> 1;
-          if (g.file_off[mid] <= q) lo = mid;
-          else hi = mid - 1;
+  if (q0 < t.len) {
+    int32_t v[kPerThread];
+    tile_load_syms(g, t, q0, v);
+    int32_t j = tile_find(L.roff, t.nr, q0);
+    int32_t next = L.roff[j + 1];
+    int64_t f = -1, f_end = 0;  // file span of the current root position
+    for (int k = 0; k < kPerThread; ++k) {
+      const int32_t qt = q0 + k;
+      if (qt >= t.len) break;
+      while (qt >= next) next = L.roff[++j + 1];
+      const int32_t r = t.r0 + j;
+      const int64_t q = t.a + qt;
+      int64_t end;
+      uint64_t wt;
+      if (r == 0) {
+        if (q >= f_end) {  // locate the file span holding q (binary search on file_off)
+          int64_t lo = 0, hi = g.F - 1;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (g.file_off[mid] <= q) lo = mid;
+            else hi = mid - 1;
+          }
+          f = lo;
+          f_end = g.file_off[f + 1];
         }
-        // skip empty spans that start at q
-        f = lo;
-        f_end = g.file_off[f + 1];
+        end = f_end;
+        wt = 1;
+      } else {
+        end = g.rule_off[r + 1];
+        wt = g.w[r];
       }
-      end = f_end;
-      wt = 1;
-    } else {
-      end = g.rule_off[r + 1];
-      wt = g.w[r];
-    }
-    if (wt == 0) continue;
-    const Piece st = piece_tail(g, len, tail, g.sym[q]);
-    const int starts = st.cnt < n - 1 ? st.cnt : n - 1;
-    // words after the piece: heads of the next pieces, at most n-1 of them
-    int32_t ahead[2];
-    int na = 0;
-    for (int64_t q2 = q + 1; q2 < end && na < n - 1; ++q2) {
-      const Piece p = piece_head(g, len, head, g.sym[q2]);
-      for (int x = 0; x < p.cnt && na < n - 1; ++x) ahead[na++] = p.w[x];
-    }
-    for (int s0 = st.cnt - starts; s0 < st.cnt; ++s0) {
-      int32_t win[3];
-      int wn = 0;
-      for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
-      for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];
-      if (wn == n) table_add(keys, vals, mask, pack_gram(win, n), wt, overflow);
+      if (wt == 0) continue;
+      const Piece st = piece_tail(g, len, tail, v[k]);
+      const int starts = st.cnt < n - 1 ? st.cnt : n - 1;
+      // words after the piece: heads of the next pieces, at most n-1 of them
+      int32_t ahead[2];
+      int na = 0;
+      for (int64_t q2 = q + 1; q2 < end && na < n - 1; ++q2) {
+        const int32_t kk = k + (int32_t)(q2 - q);
+        const Piece p = piece_head(g, len, head, (kk < kPerThread && q0 + kk < t.len) ? v[kk] : g.sym[q2]);
+        for (int x = 0; x < p.cnt && na < n - 1; ++x) ahead[na++] = p.w[x];
+      }
+      for (int s0 = st.cnt - starts; s0 < st.cnt; ++s0) {
+        int32_t win[3];
+        int wn = 0;
+        for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
+        for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];
+        if (wn == n) seq_add(L, keys, vals, mask, pack_gram(win, n), wt, overflow);
+      }
     }
   }
+  __syncthreads();
+  for (int x = threadIdx.x; x < kSeqSlots; x += blockDim.x)
+    if (L.key[x] != kEmptyKey) table_add(keys, vals, mask, L.key[x], L.val[x], overflow);
 }
 
 hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
@@ -242,12 +281,17 @@ hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, c
 }
 
 // Compaction of the occupied slots (slot order), then the caller sorts.
+// Compaction of the occupied slots (any order: a radix sort follows). Slot
+// i0 + k * 256 + thread for k < 16: the lanes of a wave read consecutive
+// slots, one line per 8 lanes.
 __global__ __launch_bounds__(256) void k_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt) {
-  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
   uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) ++c;
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = i0 + k * 256;
+    if (i < cap && __builtin_nontemporal_load(keys + i) != kEmptyKey) ++c;
+  }
   __shared__ uint32_t lds[4];
   uint32_t total;
   block_exclusive_scan_256(c, lds, &total);
@@ -256,19 +300,23 @@ __global__ __launch_bounds__(256) void k_occ_count(const uint64_t* keys, int64_t
 
 __global__ __launch_bounds__(256) void k_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap,
                                                    const uint32_t* off, uint64_t* okey, uint64_t* oval) {
-  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
+  uint64_t kv[16];
   uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) ++c;
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = i0 + k * 256;
+    kv[k] = i < cap ? __builtin_nontemporal_load(keys + i) : kEmptyKey;
+    c += kv[k] != kEmptyKey;
+  }
   __shared__ uint32_t lds[4];
   uint32_t total;
   uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (i0 + k < cap && keys[i0 + k] != kEmptyKey) {
-      okey[pos] = keys[i0 + k];
-      oval[pos] = vals[i0 + k];
+    if (kv[k] != kEmptyKey) {
+      okey[pos] = kv[k];
+      oval[pos] = vals[i0 + k * 256];
       ++pos;
     }
 }
