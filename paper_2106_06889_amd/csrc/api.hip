@@ -652,12 +652,11 @@ int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, Tv
   if (!pw || !pcnt) return oom("rule tables", 8ull * P);
   int32_t width = 1;
   for (int32_t lv = 1; lv <= D; ++lv) width = std::max(width, g->level_off[lv + 1] - g->level_off[lv]);
-  auto* list_wave = call.scratch<int32_t>(width);
-  auto* list_big = call.scratch<int32_t>(width);
-  auto* lcounts = call.scratch<int32_t>(2 * ((int64_t)D + 2));
-  if (!list_wave || !list_big || !lcounts) return oom("rule lists", 8ull * width);
+  auto* lists = call.scratch<int32_t>(4 * (int64_t)width);
+  auto* lcounts = call.scratch<int32_t>(4 * ((int64_t)D + 2));
+  if (!lists || !lcounts) return oom("rule lists", 16ull * width);
   PhaseScope t_tables(g->ctx, GTADOC_PHASE_TV_TABLES, s);
-  HIP_TRY(gt::launch_tv_tables(d, g->level_off.data(), D, toff, tsize, pw, pcnt, list_wave, list_big, lcounts, s));
+  HIP_TRY(gt::launch_tv_tables(d, g->level_off.data(), D, toff, tsize, pw, pcnt, lists, lcounts, s));
   t_tables.end();
   // 3. group every file's inputs by (file, word bucket)
   gt::TvFiles t{};

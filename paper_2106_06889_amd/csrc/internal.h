@@ -172,11 +172,11 @@ struct TvFiles {
 };
 hipError_t launch_tv_bounds(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
                             uint64_t* bound, hipStream_t s);
-// per level: rules sorted into wave / workgroup merges (lists of level width,
-// 2 (depth + 2) counters)
+// per level: rules sorted into thread / small-wave / wave / workgroup merges
+// (lists: 4 x level width, counters: 4 (depth + 2))
 hipError_t launch_tv_tables(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, const uint64_t* toff,
-                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, int32_t* list_wave, int32_t* list_big,
-                            int32_t* counts, hipStream_t s);
+                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, int32_t* lists, int32_t* counts,
+                            hipStream_t s);
 hipError_t launch_tv_units(const DevGrammar& g, int64_t* units, hipStream_t s);
 hipError_t launch_tv_count(const DevGrammar& g, const TvFiles& t, hipStream_t s);
 hipError_t launch_tv_scatter(const DevGrammar& g, const TvFiles& t, uint64_t* entries, hipStream_t s);

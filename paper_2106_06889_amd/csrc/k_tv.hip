@@ -68,15 +68,19 @@ hipError_t launch_tv_bounds(const DevGrammar& g, const int32_t* level_off_host, 
 // thread: a serial merge costs one dependent load per output entry, which is
 // milliseconds for the large tables near the top of the DAG. Per level, a
 // classification pass counts each rule's merge inputs n_in (own words plus
-// its children's table sizes) and sorts the rules into two lists:
-//  - n_in <= kTvWaveMax: one wave per rule gathers the inputs into LDS,
+// its children's table sizes) and sorts the rules into three lists:
+//  - n_in <= kTvThreadMax (most rules): one thread gathers the inputs into
+//    registers and sorts them with a fixed compare-exchange network;
+//  - n_in <= kTvWaveMax: one wave per rule gathers the inputs into LDS
+//    (a 2 KB buffer per wave up to kTvWaveSmall inputs, 16 KB above),
 //    bitonic-sorts them by word, and writes one entry per distinct word with
 //    the summed count;
 //  - larger: one workgroup per rule walks the word space in windows of 4096
 //    ids; each piece keeps a cursor, the window's inputs of every piece are
 //    summed in a dense LDS table, and its nonzero slots come out in order.
-constexpr int kTvWaveMax = 2048;   // inputs merged by one wave in LDS
-constexpr int kTvWaveWaves = 4;    // waves per workgroup of the wave merge
+constexpr int kTvThreadMax = 16;   // inputs merged by one thread in registers
+constexpr int kTvWaveSmall = 256;  // inputs merged by one wave with a small LDS buffer
+constexpr int kTvWaveMax = 2048;   // inputs merged by one wave with a large LDS buffer
 constexpr int kTvBigThreads = 1024;
 constexpr int kTvBigPieces = 4096;  // body symbols the workgroup merge keeps cursors for
 
@@ -96,8 +100,8 @@ __device__ __forceinline__ uint32_t first_at_least(const uint32_t* w, uint32_t l
 }
 
 __global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t* rules, int32_t n,
-                                                     const uint32_t* tsize, int32_t* list_wave, int32_t* list_big,
-                                                     int32_t* counts) {
+                                                     const uint32_t* tsize, int32_t* list_thread, int32_t* list_small,
+                                                     int32_t* list_wave, int32_t* list_big, int32_t* counts) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < n;
   const int32_t r = live ? rules[i] : 0;
@@ -113,17 +117,92 @@ __global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t
   }
   // one counter atomic per wave and list (a per-thread atomic on one address
   // serializes millions of them)
-  const bool small = n_in <= (uint64_t)kTvWaveMax;
-  const int32_t at_w = wave_append(live && small, &counts[0]);
-  const int32_t at_b = wave_append(live && !small, &counts[1]);
-  if (live && small) list_wave[at_w] = r;
-  if (live && !small) list_big[at_b] = r;
+  const int tier = n_in <= (uint64_t)kTvThreadMax ? 0 : n_in <= (uint64_t)kTvWaveSmall ? 1
+                   : n_in <= (uint64_t)kTvWaveMax ? 2 : 3;
+  const int32_t at0 = wave_append(live && tier == 0, &counts[0]);
+  const int32_t at1 = wave_append(live && tier == 1, &counts[1]);
+  const int32_t at2 = wave_append(live && tier == 2, &counts[2]);
+  const int32_t at3 = wave_append(live && tier == 3, &counts[3]);
+  if (live) {
+    if (tier == 0) list_thread[at0] = r;
+    else if (tier == 1) list_small[at1] = r;
+    else if (tier == 2) list_wave[at2] = r;
+    else list_big[at3] = r;
+  }
 }
 
-__global__ __launch_bounds__(64 * kTvWaveWaves) void k_tv_merge_wave(DevGrammar g, const int32_t* list,
-                                                                     const int32_t* count, const uint64_t* toff,
-                                                                     uint32_t* tsize, uint32_t* pw, uint32_t* pc) {
-  __shared__ uint64_t buf[kTvWaveWaves][kTvWaveMax];  // (word << 32 | count) per input
+// One thread per rule with at most kTvThreadMax inputs: the inputs (word <<
+// 32 | count) are gathered into a register array (each insert a fixed loop
+// of selects, so the array is never indexed dynamically), sorted by a
+// bitonic network over the 16 slots, and the runs of equal words summed.
+__device__ __forceinline__ void reg_insert(uint64_t (&e)[kTvThreadMax], int at, uint64_t x) {
+#pragma unroll
+  for (int i = 0; i < kTvThreadMax; ++i)
+    if (i == at) e[i] = x;
+}
+
+__global__ __launch_bounds__(256) void k_tv_merge_thread(DevGrammar g, const int32_t* list, const int32_t* count,
+                                                         const uint64_t* toff, uint32_t* tsize, uint32_t* pw,
+                                                         uint32_t* pc) {
+  const int32_t nr = *count;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < nr; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = list[j];
+    const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+    uint64_t e[kTvThreadMax];
+#pragma unroll
+    for (int i = 0; i < kTvThreadMax; ++i) e[i] = ~0ull;
+    int n = 0;
+    for (int64_t q = a; q < b; ++q) {
+      const int32_t s = g.sym[q];
+      if (s >= 0) {
+        reg_insert(e, n++, ((uint64_t)(uint32_t)s << 32) | 1u);
+      } else {
+        const uint32_t t = tsize[-s];
+        const uint64_t o = toff[-s];
+        for (uint32_t x = 0; x < t && n < kTvThreadMax; ++x) reg_insert(e, n++, ((uint64_t)pw[o + x] << 32) | pc[o + x]);
+      }
+    }
+#pragma unroll
+    for (int k = 2; k <= kTvThreadMax; k <<= 1) {
+#pragma unroll
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+#pragma unroll
+        for (int i = 0; i < kTvThreadMax; ++i) {
+          const int l = i ^ jj;
+          if (l > i) {
+            const uint64_t u = e[i], v = e[l];
+            const bool swap = ((i & k) == 0) ? (u > v) : (u < v);
+            e[i] = swap ? v : u;
+            e[l] = swap ? u : v;
+          }
+        }
+      }
+    }
+    const uint64_t out = toff[r];
+    uint32_t m = 0, run_w = 0xffffffffu, run_c = 0;
+#pragma unroll
+    for (int i = 0; i < kTvThreadMax; ++i) {
+      const uint32_t wd = (uint32_t)(e[i] >> 32), c = (uint32_t)e[i];
+      if (i < n) {
+        if (wd != run_w) {
+          if (run_c) pw[out + m] = run_w, pc[out + m] = run_c, ++m;
+          run_w = wd, run_c = c;
+        } else {
+          run_c += c;
+        }
+      }
+    }
+    if (run_c) pw[out + m] = run_w, pc[out + m] = run_c, ++m;
+    tsize[r] = m;
+  }
+}
+
+template <int kMax, int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void k_tv_merge_wave(DevGrammar g, const int32_t* list, const int32_t* count,
+                                                               const uint64_t* toff, uint32_t* tsize, uint32_t* pw,
+                                                               uint32_t* pc) {
+  constexpr int kTvWaveWaves = kWaves;
+  __shared__ uint64_t buf[kWaves][kMax];  // (word << 32 | count) per input
   const int wave = threadIdx.x >> 6, lane = lane_id();
   uint64_t* e = buf[wave];
   const int32_t nr = *count;
@@ -388,19 +467,30 @@ __global__ __launch_bounds__(kTvBigThreads) void k_tv_merge_big(DevGrammar g, co
 }
 
 hipError_t launch_tv_tables(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, const uint64_t* toff,
-                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, int32_t* list_wave, int32_t* list_big,
-                            int32_t* counts, hipStream_t s) {
-  hipError_t e = launch_fill_i32(counts, 2 * ((int64_t)depth + 2), 0, s);
+                            uint32_t* tsize, uint32_t* pw, uint32_t* pc, int32_t* lists, int32_t* counts,
+                            hipStream_t s) {
+  hipError_t e = launch_fill_i32(counts, 4 * ((int64_t)depth + 2), 0, s);
   if (e != hipSuccess) return e;
   for (int32_t d = depth; d >= 1; --d) {
     const int32_t lo = level_off_host[d], hi = level_off_host[d + 1];
     if (hi <= lo) continue;
     const int32_t n = hi - lo;
-    int32_t* c = counts + 2 * d;
-    k_tv_classify<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, n, tsize, list_wave, list_big, c);
-    const int32_t gw = (n + kTvWaveWaves - 1) / kTvWaveWaves;
-    k_tv_merge_wave<<<(unsigned)(gw < 4096 ? gw : 4096), 64 * kTvWaveWaves, 0, s>>>(g, list_wave, c, toff, tsize, pw, pc);
-    k_tv_merge_big<<<(unsigned)(n < 1024 ? n : 1024), kTvBigThreads, 0, s>>>(g, list_big, c + 1, toff, tsize, pw, pc);
+    int32_t* c = counts + 4 * d;
+    int32_t* list_thread = lists;
+    int32_t* list_small = lists + n;
+    int32_t* list_wave = lists + 2 * (int64_t)n;
+    int32_t* list_big = lists + 3 * (int64_t)n;
+    k_tv_classify<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, n, tsize, list_thread, list_small,
+                                                               list_wave, list_big, c);
+    const int32_t g0 = (n + 255) / 256;
+    k_tv_merge_thread<<<(unsigned)(g0 < 4096 ? g0 : 4096), 256, 0, s>>>(g, list_thread, c + 0, toff, tsize, pw, pc);
+    const int32_t g1 = (n + 15) / 16;
+    k_tv_merge_wave<kTvWaveSmall, 16><<<(unsigned)(g1 < 4096 ? g1 : 4096), 1024, 0, s>>>(g, list_small, c + 1, toff,
+                                                                                           tsize, pw, pc);
+    const int32_t g2 = (n + 3) / 4;
+    k_tv_merge_wave<kTvWaveMax, 4><<<(unsigned)(g2 < 4096 ? g2 : 4096), 256, 0, s>>>(g, list_wave, c + 2, toff, tsize,
+                                                                                       pw, pc);
+    k_tv_merge_big<<<(unsigned)(n < 1024 ? n : 1024), kTvBigThreads, 0, s>>>(g, list_big, c + 3, toff, tsize, pw, pc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
