@@ -35,13 +35,20 @@ __global__ void k_tv_bound_level(DevGrammar g, const int32_t* rules, int32_t n, 
   if (i >= n) return;
   const int32_t r = rules[i];
   uint64_t L = 0, B = 0;
-  for (int64_t q = g.rule_off[r]; q < g.rule_off[r + 1]; ++q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      ++L, ++B;
-    } else {
-      L += len[-s];
-      B += bound[-s];
+  const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  for (int64_t q0 = a; q0 < b; q0 += 8) {  // 8 symbols, then their children's figures, in flight together
+    int32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = q0 + k < b ? g.sym[q0 + k] : 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (q0 + k >= b) continue;
+      if (v[k] >= 0) {
+        ++L, ++B;
+      } else {
+        L += len[-v[k]];
+        B += bound[-v[k]];
+      }
     }
   }
   if (B > L) B = L;
@@ -119,15 +126,32 @@ __global__ __launch_bounds__(256) void k_tv_classify(DevGrammar g, const int32_t
   // serializes millions of them)
   const int tier = n_in <= (uint64_t)kTvThreadMax ? 0 : n_in <= (uint64_t)kTvWaveSmall ? 1
                    : n_in <= (uint64_t)kTvWaveMax ? 2 : 3;
-  const int32_t at0 = wave_append(live && tier == 0, &counts[0]);
-  const int32_t at1 = wave_append(live && tier == 1, &counts[1]);
-  const int32_t at2 = wave_append(live && tier == 2, &counts[2]);
-  const int32_t at3 = wave_append(live && tier == 3, &counts[3]);
+  // appends aggregated per workgroup: one global atomic per workgroup and
+  // list (per wave they still made ~60K same-address atomics on a 4M-rule level)
+  __shared__ int32_t wcnt[4], wbase[4];
+  if (threadIdx.x < 4) wcnt[threadIdx.x] = 0;
+  __syncthreads();
+  int32_t my = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const uint64_t mask = __ballot(live && tier == t);
+    if (mask) {
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      int32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(&wcnt[t], (int32_t)__popcll(mask));
+      base = __shfl(base, leader);
+      if (live && tier == t) my = base + (int32_t)__popcll(mask & lanes_below());
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) wbase[threadIdx.x] = wcnt[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], wcnt[threadIdx.x]) : 0;
+  __syncthreads();
   if (live) {
-    if (tier == 0) list_thread[at0] = r;
-    else if (tier == 1) list_small[at1] = r;
-    else if (tier == 2) list_wave[at2] = r;
-    else list_big[at3] = r;
+    const int32_t at = wbase[tier] + my;
+    if (tier == 0) list_thread[at] = r;
+    else if (tier == 1) list_small[at] = r;
+    else if (tier == 2) list_wave[at] = r;
+    else list_big[at] = r;
   }
 }
 
