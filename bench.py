@@ -107,8 +107,13 @@ def measured_traffic(phase: str, workload: str):
             rec = json.loads(line[len("traffic-record: "):])
             if rec.get("kernel") != kernel or rec.get("workload") != workload:
                 continue
-            src = os.path.join(ROOT, rec["source"])
-            if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["source_sha256"]:
+            h = hashlib.sha256()
+            try:
+                for src in rec["sources"]:
+                    h.update(open(os.path.join(ROOT, src), "rb").read())
+            except OSError:
+                continue
+            if h.hexdigest() == rec["sources_sha256"]:
                 return int(rec["traffic_bytes_per_launch"])
     return None
 
