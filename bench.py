@@ -105,7 +105,7 @@ def measured_traffic(phase: str, workload: str):
             if not line.startswith("traffic-record: "):
                 continue
             rec = json.loads(line[len("traffic-record: "):])
-            if rec.get("kernel") != kernel or rec.get("workload") != workload:
+            if rec.get("kernel") != kernel or rec.get("workload") != workload or "sources" not in rec:
                 continue
             h = hashlib.sha256()
             try:
