@@ -389,7 +389,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
   uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
-                                                    nbR + gt::scan_scratch_entries(nbR)}));
+                                                    nbR + gt::scan_scratch_entries(nbR) + 2}));
   if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc || !sums ||
       (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));

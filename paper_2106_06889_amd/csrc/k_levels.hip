@@ -147,6 +147,35 @@ __device__ __forceinline__ bool agg_add(LevelLds& L, int32_t c, uint64_t w) {
 // working workgroups faster and the level walk ~35% shorter.
 __device__ __forceinline__ void grid_barrier() { cg::this_grid().sync(); }
 
+// Barrier among the first kMidBlocks workgroups (the others have left): a
+// counter and a generation word in device memory (zero at launch). Every
+// thread releases its own writes at device scope; thread 0 arrives, the last
+// arriver resets the counter and bumps the generation, the others poll it
+// without acquiring (an acquire per poll would invalidate the caches under
+// the working workgroups), then thread 0 acquires once. Per-level timestamps
+// showed narrow levels costing ~40 us on the full grid and ~20 us on 32-64
+// workgroups.
+constexpr int kMidBlocks = 32;
+constexpr int32_t kMidRules = 48 * 1024;  // levels narrower than this run on kMidBlocks workgroups
+
+__device__ __forceinline__ void mid_barrier(uint32_t* bar, uint32_t& gen) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t g0 = gen;
+    const uint32_t a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == kMidBlocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  ++gen;
+  __syncthreads();
+}
+
 // The workgroup's list of level d+1 goes after hi with one global atomic.
 __device__ __forceinline__ void level_list_out(DevGrammar& g, int32_t* level_cnt, LevelLds& L, int32_t d, int32_t hi) {
   __syncthreads();
@@ -367,7 +396,7 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
 constexpr int32_t kTailRules = 4 * kLevelThreads;
 
 __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt,
-                                                          LoadCounters* lc, WideBufs wb) {
+                                                          LoadCounters* lc, WideBufs wb, uint32_t* bar) {
   __shared__ LevelLds L;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
@@ -379,7 +408,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   agg_reset(L);
   bool agg_clean = true;
   // wide levels: the whole grid, a grid barrier between levels
-  while (lo < hi && (hi - lo >= kTailRules || gridDim.x == 1)) {
+  const bool shrink = gridDim.x > (unsigned)kMidBlocks;
+  while (lo < hi && (hi - lo >= (shrink ? kMidRules : kTailRules) || gridDim.x == 1)) {
     if (wb.ew && hi - lo >= wb.min_rules) {
       wide_scatter(g, wb, L, lo, hi, tid, nthreads, tokens);
       grid_barrier();
@@ -398,6 +428,25 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
     lo = hi;
     hi += next;
     ++d;
+  }
+  // mid levels: the first kMidBlocks workgroups, the others leave
+  if (shrink && blockIdx.x < (unsigned)kMidBlocks) {
+    if (!agg_clean) agg_reset(L), agg_clean = true;
+    const int64_t mtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t mthreads = (int64_t)kMidBlocks * blockDim.x;
+    uint32_t gen = 0;
+    while (lo < hi && hi - lo >= kTailRules) {
+      level_round(g, pend, level_cnt, L, lo, hi, d, mtid, mthreads, tokens);
+      mid_barrier(bar, gen);
+      const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (mtid == 0) {
+        g.level_off[d] = lo;
+        g.level_off[d + 1] = hi;
+      }
+      lo = hi;
+      hi += next;
+      ++d;
+    }
   }
   // narrow levels: workgroup 0 alone
   if (blockIdx.x == 0) {
@@ -461,6 +510,7 @@ __global__ __launch_bounds__(256) void k_wide_caps(const int32_t* pend, int64_t 
 
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
                              uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s) {
+  const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
   WideBufs wb = wide;
   if (wb.ew) {
     // bucket regions: exclusive scan of the capacities; both cursors start there
@@ -481,7 +531,10 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_
   const int64_t cap = cus;  // one workgroup per CU: few participants in every grid barrier
   const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
   DevGrammar gg = g;
-  void* args[] = {&gg, &pend, &level_cnt, &lc, &wb};
+  uint32_t* bar = scratch + nb + scan_sums_entries(nb);  // 2 words after the frontier scan's scratch
+  e = launch_fill_i32(reinterpret_cast<int32_t*>(bar), 2, 0, s);
+  if (e != hipSuccess) return e;
+  void* args[] = {&gg, &pend, &level_cnt, &lc, &wb, &bar};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(kLevelThreads), args, 0,
                                     s);
 }
