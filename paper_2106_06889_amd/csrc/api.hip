@@ -681,7 +681,10 @@ int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, Tv
   PhaseScope t_reduce(g->ctx, GTADOC_PHASE_TV_REDUCE, s);
   HIP_TRY(gt::launch_tv_scatter(d, t, entries, s));
   // 4. dense LDS sums per group, then the CSR
-  HIP_TRY(gt::launch_tv_reduce(d, t, entries, E, nnz, s));
+  auto* glists = call.scratch<int32_t>(F * (int64_t)nb);
+  auto* gcounts = call.scratch<int32_t>(1);
+  if (!glists || !gcounts) return oom("term vector group lists", 4ull * F * nb);
+  HIP_TRY(gt::launch_tv_reduce(d, t, entries, E, nnz, glists, gcounts, s));
   t_reduce.end();
   auto* noff = call.scratch<uint32_t>(F * (int64_t)nb + 1);
   if (!noff) return oom("term vector offsets", 4ull * F * nb);

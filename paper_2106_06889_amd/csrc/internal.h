@@ -181,7 +181,7 @@ hipError_t launch_tv_units(const DevGrammar& g, int64_t* units, hipStream_t s);
 hipError_t launch_tv_count(const DevGrammar& g, const TvFiles& t, hipStream_t s);
 hipError_t launch_tv_scatter(const DevGrammar& g, const TvFiles& t, uint64_t* entries, hipStream_t s);
 hipError_t launch_tv_reduce(const DevGrammar& g, const TvFiles& t, uint64_t* entries, int64_t E, uint32_t* nnz,
-                            hipStream_t s);
+                            int32_t* lists, int32_t* counts, hipStream_t s);
 hipError_t launch_tv_emit(const DevGrammar& g, const TvFiles& t, const uint64_t* entries, int64_t E,
                           const uint32_t* nnz, const uint32_t* noff, uint32_t* out_word, uint64_t* out_cnt,
                           int64_t* out_off, hipStream_t s);

@@ -639,35 +639,124 @@ __device__ __forceinline__ int64_t group_start(const DevGrammar& g, const TvFile
   return slot < nb * t.nunits ? (int64_t)t.table[slot] : E;
 }
 
-// Pass 3: sum each group in a dense LDS table; the nonzero slots are written
-// back over the group's own entries in word order, packed (word << 32 |
-// count), and their number to nnz[group]. Workgroup j takes the groups that
-// start in [j * kTvChunk, (j+1) * kTvChunk) of the entry array.
+// Pass 3: sum each group (file f, word bucket b); the distinct words come
+// out in word order, written back over the group's own entries as (word <<
+// 32 | count), and their number to nnz[group]. A dense 4096-slot LDS table
+// per group costs F x V slot visits whatever the group sizes (most groups
+// hold a few hundred entries), so groups are merged by size:
+//  - up to kTvGroupSmall entries: one wave per group sorts them in LDS
+//    (bitonic, by low word id) and sums the runs of equal words;
+//  - larger: one workgroup per group, dense LDS table.
+// (A middle class sorting up to 2048 entries per wave was measured slower
+// than the dense table.) The wave pass hands the larger groups on in a list,
+// one atomic per workgroup.
 constexpr int kTvThreads = 1024;
-constexpr int64_t kTvChunk = 16 * kTvThreads;
+constexpr int kTvGroupSmall = 256;
 
-__global__ __launch_bounds__(kTvThreads) void k_tv_reduce(DevGrammar g, TvFiles t, uint64_t* entries, int64_t E,
-                                                          uint32_t* nnz) {
-  __shared__ uint32_t cnt[kWcBucket];
-  __shared__ int64_t first_group;
-  __shared__ uint32_t wsum[kTvThreads / 64];
-  const int64_t ngroups = g.F * (int64_t)t.nb;
-  const int64_t c_lo = (int64_t)blockIdx.x * kTvChunk, c_hi = c_lo + kTvChunk;
-  if (threadIdx.x == 0) {
-    int64_t lo = 0, hi = ngroups;  // first group starting at or after c_lo
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (group_start(g, t, mid, E) < c_lo) lo = mid + 1;
-      else hi = mid;
+template <int kMax, int kWaves, bool kFromList>
+__global__ __launch_bounds__(64 * kWaves) void k_tv_group_merge(DevGrammar g, TvFiles t, uint64_t* entries, int64_t E,
+                                                                uint32_t* nnz, const int32_t* list, const int32_t* count,
+                                                                int32_t* next_list, int32_t* next_count) {
+  __shared__ uint64_t buf[kWaves][kMax];
+  __shared__ int32_t handed[kWaves][64];  // groups for the next size class, gathered per wave
+  __shared__ int32_t handed_n[kWaves], handed_base;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  uint64_t* e = buf[wave];
+  int32_t nh = 0;  // this wave's handed groups (uniform in the wave)
+  const int64_t ngroups = kFromList ? (int64_t)*count : g.F * (int64_t)t.nb;
+  for (int64_t j = (int64_t)blockIdx.x * kWaves + wave; j < ngroups; j += (int64_t)gridDim.x * kWaves) {
+    const int64_t grp = kFromList ? (int64_t)list[j] : j;
+    const int64_t lo = group_start(g, t, grp, E), hi = group_start(g, t, grp + 1, E);
+    const uint32_t n = (uint32_t)(hi - lo);
+    if (n > (uint32_t)kMax) {  // uniform for the wave: hand the group on
+      if (nh == 64) {  // buffer full: flush it with one atomic
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(next_count, 64);
+        base = __shfl(base, 0);
+        next_list[base + lane] = handed[wave][lane];
+        wave_lds_sync();
+        nh = 0;
+      }
+      if (lane == 0) handed[wave][nh] = (int32_t)grp;
+      ++nh;
+      wave_lds_sync();
+      continue;
     }
-    first_group = lo;
+    if (n == 0) continue;  // nnz stays 0
+    // (low id << 32 | count), sorted by low id, so equal words are adjacent
+    uint32_t P = 1;
+    while (P < n) P <<= 1;
+    for (uint32_t x = lane; x < P; x += 64) {
+      if (x < n) {
+        const uint64_t v = entries[lo + x];
+        e[x] = ((v & (kWcBucket - 1)) << 32) | (v >> kWcBits);
+      } else {
+        e[x] = ~0ull;
+      }
+    }
+    wave_lds_sync();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t x = lane; x < P; x += 64) {
+          const uint32_t l = x ^ jj;
+          if (l > x) {
+            const uint64_t u = e[x], v = e[l];
+            if ((u > v) == ((x & k) == 0)) e[x] = v, e[l] = u;
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    const uint32_t C = (n + 63) / 64;
+    const uint32_t c0 = lane * C < n ? lane * C : n, c1 = c0 + C < n ? c0 + C : n;
+    uint32_t h = 0;
+    for (uint32_t x = c0; x < c1; ++x) h += x == 0 || (e[x] >> 32) != (e[x - 1] >> 32);
+    uint32_t incl = h;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    uint32_t o = incl - h;
+    const uint64_t wbase = (uint64_t)(grp % t.nb) * kWcBucket;
+    for (uint32_t x = c0; x < c1; ++x) {
+      const uint32_t low = (uint32_t)(e[x] >> 32);
+      if (x == 0 || low != (uint32_t)(e[x - 1] >> 32)) {
+        uint32_t sum = 0;
+        for (uint32_t y = x; y < n && (uint32_t)(e[y] >> 32) == low; ++y) sum += (uint32_t)e[y];
+        entries[lo + o] = ((wbase + low) << 32) | sum;
+        ++o;
+      }
+    }
+    if (lane == 63) nnz[grp] = incl;
+    wave_lds_sync();  // the next group reuses the buffer
   }
+  // the handed groups of the whole workgroup, with one atomic
+  if (lane == 0) handed_n[wave] = nh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < kWaves; ++w) tot += handed_n[w];
+    handed_base = tot ? atomicAdd(next_count, tot) : 0;
+  }
+  __syncthreads();
+  int32_t off = handed_base;
+  for (int w = 0; w < wave; ++w) off += handed_n[w];
+  if (lane < nh) next_list[off + lane] = handed[wave][lane];
+}
+
+// Groups too large for a wave: one workgroup each, dense LDS table.
+__global__ __launch_bounds__(kTvThreads) void k_tv_group_dense(DevGrammar g, TvFiles t, uint64_t* entries, int64_t E,
+                                                               uint32_t* nnz, const int32_t* list,
+                                                               const int32_t* count) {
+  __shared__ uint32_t cnt[kWcBucket];
+  __shared__ uint32_t wsum[kTvThreads / 64];
   for (int i = threadIdx.x; i < kWcBucket; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
-  for (int64_t s = first_group; s < ngroups; ++s) {
-    const int64_t lo = group_start(g, t, s, E);
-    if (lo >= c_hi) break;  // empty groups past the end keep nnz = 0
-    const int64_t hi = group_start(g, t, s + 1, E);
+  const int32_t ng = *count;
+  for (int32_t j = blockIdx.x; j < ng; j += gridDim.x) {
+    const int64_t s = list[j];
+    const int64_t lo = group_start(g, t, s, E), hi = group_start(g, t, s + 1, E);
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
       const uint64_t e = entries[i];
       atomicAdd(&cnt[e & (kWcBucket - 1)], (uint32_t)(e >> kWcBits));
@@ -677,7 +766,6 @@ __global__ __launch_bounds__(kTvThreads) void k_tv_reduce(DevGrammar g, TvFiles 
     uint32_t c4[4], nz = 0;
 #pragma unroll
     for (int x = 0; x < 4; ++x) c4[x] = cnt[threadIdx.x * 4 + x], nz += c4[x] != 0;
-    // block exclusive scan of nz (16 waves)
     uint32_t incl = nz;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -703,12 +791,19 @@ __global__ __launch_bounds__(kTvThreads) void k_tv_reduce(DevGrammar g, TvFiles 
   }
 }
 
+// lists: F * nb group ids; counts: 1 counter.
 hipError_t launch_tv_reduce(const DevGrammar& g, const TvFiles& t, uint64_t* entries, int64_t E, uint32_t* nnz,
-                            hipStream_t s) {
-  const int64_t blocks = E > 0 ? (E + kTvChunk - 1) / kTvChunk : 1;
-  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(nnz), g.F * (int64_t)t.nb, 0, s);
-  if (e != hipSuccess) return e;
-  k_tv_reduce<<<(unsigned)blocks, kTvThreads, 0, s>>>(g, t, entries, E, nnz);
+                            int32_t* lists, int32_t* counts, hipStream_t s) {
+  const int64_t ngroups = g.F * (int64_t)t.nb;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(nnz), ngroups, 0, s);
+  if (e == hipSuccess) e = launch_fill_i32(counts, 1, 0, s);
+  if (e != hipSuccess || ngroups == 0) return e;
+  int32_t* l1 = lists;
+  const int64_t g0 = (ngroups + 15) / 16;
+  k_tv_group_merge<kTvGroupSmall, 16, false><<<(unsigned)(g0 < 4096 ? g0 : 4096), 1024, 0, s>>>(
+      g, t, entries, E, nnz, nullptr, nullptr, l1, counts + 0);
+  k_tv_group_dense<<<(unsigned)(ngroups < 2048 ? ngroups : 2048), kTvThreads, 0, s>>>(g, t, entries, E, nnz, l1,
+                                                                                   counts + 0);
   return hipGetLastError();
 }
 
