@@ -836,18 +836,37 @@ hipError_t launch_tv_emit(const DevGrammar& g, const TvFiles& t, const uint64_t*
 // Inverted index: stable radix sort of (word, file) by word, then the word
 // offsets from the run boundaries.
 // ---------------------------------------------------------------------------
-__global__ void k_ii_pairs(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, int64_t nnz, uint64_t* key,
-                           uint32_t* file) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nnz) return;
-  int64_t lo = 0, hi = F - 1;  // file f with tv_off[f] <= i < tv_off[f+1]
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (tv_off[mid] <= i) lo = mid;
-    else hi = mid - 1;
+// (word, file) pairs of the term vector. A workgroup takes 4096 consecutive
+// entries: the files of its first and last entry are found once (binary
+// search on tv_off), and each entry searches only that range (nearly always
+// one file), instead of a full search per entry.
+__global__ __launch_bounds__(256) void k_ii_pairs(const int64_t* tv_off, int64_t F, const uint32_t* tv_word,
+                                                  int64_t nnz, uint64_t* key, uint32_t* file) {
+  __shared__ int64_t frange[2];
+  const int64_t c0 = (int64_t)blockIdx.x * 4096;
+  const int64_t c1 = c0 + 4096 < nnz ? c0 + 4096 : nnz;
+  if (threadIdx.x < 2) {
+    const int64_t i = threadIdx.x == 0 ? c0 : c1 - 1;
+    int64_t lo = 0, hi = F - 1;  // file f with tv_off[f] <= i < tv_off[f+1] (the last such f)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (tv_off[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    frange[threadIdx.x] = lo;
   }
-  key[i] = tv_word[i];
-  file[i] = (uint32_t)lo;
+  __syncthreads();
+  const int64_t flo = frange[0], fhi = frange[1];
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    int64_t lo = flo, hi = fhi;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (tv_off[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    key[i] = tv_word[i];
+    file[i] = (uint32_t)lo;
+  }
 }
 
 __global__ void k_ii_offsets(const uint64_t* key, int64_t nnz, int32_t V, int64_t* off) {
@@ -863,7 +882,7 @@ hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, 
                      uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout, uint32_t* file_out,
                      const int64_t* num, uint32_t* hist, int64_t* ii_off, hipStream_t s) {
   if (nnz > 0) {
-    k_ii_pairs<<<(unsigned)((nnz + 255) / 256), 256, 0, s>>>(tv_off, F, tv_word, nnz, k0, v0);
+    k_ii_pairs<<<(unsigned)((nnz + 4095) / 4096), 256, 0, s>>>(tv_off, F, tv_word, nnz, k0, v0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int b = 1;
