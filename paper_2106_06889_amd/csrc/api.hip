@@ -833,22 +833,24 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
     g->seq_len = len, g->seq_head = head, g->seq_tail = tail;
   }
   // graph traversal phase: owned windows into an exact table sized from the
-  // per-rule bound (at most n-1 windows start at every body position)
+  // per-rule bound (at most n-1 windows start at every body position): the
+  // table holds at least as many slots as there can be distinct keys (the
+  // load factor stays under 1; on text, distinct n-grams are far fewer than
+  // windows, so it is about 0.5)
   const uint64_t bound = (uint64_t)(n - 1) * (uint64_t)S + 1;
   uint64_t cap = 1024;
-  while (cap < 2 * bound) cap <<= 1;
-  auto* keys = call.scratch<uint64_t>((int64_t)cap);
-  auto* vals = call.scratch<uint64_t>((int64_t)cap);
+  while (cap < bound) cap <<= 1;
+  auto* table = call.scratch<uint64_t>(2 * (int64_t)cap);
   const int64_t nb = ((int64_t)cap + 4095) / 4096;
   auto* cnt = call.scratch<uint32_t>(nb + gt::scan_scratch_entries(nb));
   auto* flags = call.scratch<int64_t>(2);  // [0] distinct keys, [1] overflow flag
-  if (!keys || !vals || !cnt || !flags) return oom("sequence table", 16 * cap);
+  if (!table || !cnt || !flags) return oom("sequence table", 16 * cap);
   HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(flags), 4, 0, s));
   PhaseScope t_win(g->ctx, GTADOC_PHASE_SEQ_WINDOWS, s);
-  HIP_TRY(gt::launch_seq_windows(d, n, g->seq_len, g->seq_head, g->seq_tail, keys, vals, cap,
+  HIP_TRY(gt::launch_seq_windows(d, n, g->seq_len, g->seq_head, g->seq_tail, table, cap,
                                  reinterpret_cast<uint32_t*>(flags + 1), s));
   t_win.end();
-  HIP_TRY(gt::launch_occ_count(keys, (int64_t)cap, cnt, flags, cnt + nb, s));
+  HIP_TRY(gt::launch_occ_count(table, (int64_t)cap, cnt, flags, cnt + nb, s));
   auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
   HIP_TRY(hipMemcpyAsync(pc, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -869,7 +871,7 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
     return oom("sequence result", 48 * (uint64_t)U);
   }
   if (U > 0) {
-    hipError_t e = gt::launch_occ_write(keys, vals, (int64_t)cap, cnt, k0, v0, s);
+    hipError_t e = gt::launch_occ_write(table, (int64_t)cap, cnt, k0, v0, s);
     if (e == hipSuccess)
       e = gt::launch_sort_keys_u64(k0, v0, k1, v1, flags, U, gram_byte_mask(n, d.V), hist, okey, oval, s);
     if (e != hipSuccess) {

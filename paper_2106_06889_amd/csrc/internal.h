@@ -194,13 +194,13 @@ hipError_t launch_scan_u32_ext(uint32_t* a, int64_t n, int64_t* total, uint32_t*
 // sequence count
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
                            int32_t* head, int32_t* tail, hipStream_t s);
+// the exact table interleaves key and count: 2 * cap uint64
 hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
-                              const int32_t* tail, uint64_t* keys, uint64_t* vals, uint64_t cap, uint32_t* overflow,
-                              hipStream_t s);
-hipError_t launch_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
+                              const int32_t* tail, uint64_t* table, uint64_t cap, uint32_t* overflow, hipStream_t s);
+hipError_t launch_occ_count(const uint64_t* table, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
                             hipStream_t s);
-hipError_t launch_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap, const uint32_t* off,
-                            uint64_t* okey, uint64_t* oval, hipStream_t s);
+hipError_t launch_occ_write(const uint64_t* table, int64_t cap, const uint32_t* off, uint64_t* okey, uint64_t* oval,
+                            hipStream_t s);
 hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
                                 uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s);
 hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,

@@ -114,18 +114,20 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 
 // Lock-free insert-or-add: the first thread to CAS an empty slot owns it for
 // that key; every occurrence then adds its weight to the slot's count.
-__device__ __forceinline__ void table_add(uint64_t* keys, uint64_t* vals, uint64_t mask, uint64_t key, uint64_t w,
+// The table interleaves key and count: slot h is table[2h] (key) and
+// table[2h + 1] (count), one cache line for both.
+__device__ __forceinline__ void table_add(uint64_t* table, uint64_t mask, uint64_t key, uint64_t w,
                                           uint32_t* overflow) {
   uint64_t h = mix64(key) & mask;
   for (uint64_t p = 0; p <= mask; ++p) {
-    uint64_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t k = __hip_atomic_load(&table[2 * h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (k == kEmptyKey) {
-      k = atomicCAS(reinterpret_cast<unsigned long long*>(&keys[h]), (unsigned long long)kEmptyKey,
+      k = atomicCAS(reinterpret_cast<unsigned long long*>(&table[2 * h]), (unsigned long long)kEmptyKey,
                     (unsigned long long)key);
       if (k == kEmptyKey) k = key;
     }
     if (k == key) {
-      atomicAdd(reinterpret_cast<unsigned long long*>(&vals[h]), (unsigned long long)w);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&table[2 * h + 1]), (unsigned long long)w);
       return;
     }
     h = (h + 1) & mask;
@@ -187,7 +189,7 @@ struct SeqLds {
   uint64_t val[kSeqSlots];
 };
 
-__device__ __forceinline__ void seq_add(SeqLds& L, uint64_t* keys, uint64_t* vals, uint64_t mask, uint64_t key,
+__device__ __forceinline__ void seq_add(SeqLds& L, uint64_t* table, uint64_t mask, uint64_t key,
                                         uint64_t w, uint32_t* overflow) {
   const uint32_t h = (uint32_t)(mix64(key) >> 40) & (kSeqSlots - 1);
 #pragma unroll
@@ -202,14 +204,14 @@ __device__ __forceinline__ void seq_add(SeqLds& L, uint64_t* keys, uint64_t* val
       return;
     }
   }
-  table_add(keys, vals, mask, key, w, overflow);
+  table_add(table, mask, key, w, overflow);
 }
 
 // Owned windows, position-parallel over the tiles of all bodies. The root is
 // split at file boundaries: windows never cross files.
 __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int n, const uint64_t* len,
-                                                              const int32_t* head, const int32_t* tail, uint64_t* keys,
-                                                              uint64_t* vals, uint64_t mask, uint32_t* overflow) {
+                                                              const int32_t* head, const int32_t* tail,
+                                                              uint64_t* table, uint64_t mask, uint32_t* overflow) {
   __shared__ SeqLds L;
   for (int x = threadIdx.x; x < kSeqSlots; x += blockDim.x) L.key[x] = kEmptyKey, L.val[x] = 0;
   const Tile t = tile_begin(g, blockIdx.x, L.roff);  // (synchronizes)
@@ -261,22 +263,29 @@ __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int 
         int wn = 0;
         for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
         for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];
-        if (wn == n) seq_add(L, keys, vals, mask, pack_gram(win, n), wt, overflow);
+        if (wn == n) seq_add(L, table, mask, pack_gram(win, n), wt, overflow);
       }
     }
   }
   __syncthreads();
   for (int x = threadIdx.x; x < kSeqSlots; x += blockDim.x)
-    if (L.key[x] != kEmptyKey) table_add(keys, vals, mask, L.key[x], L.val[x], overflow);
+    if (L.key[x] != kEmptyKey) table_add(table, mask, L.key[x], L.val[x], overflow);
+}
+
+__global__ void k_fill_table(uint64_t* table, int64_t cap) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x) {
+    table[2 * i] = kEmptyKey;
+    table[2 * i + 1] = 0;
+  }
 }
 
 hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
-                              const int32_t* tail, uint64_t* keys, uint64_t* vals, uint64_t cap, uint32_t* overflow,
-                              hipStream_t s) {
-  hipError_t e = launch_fill_u64(keys, (int64_t)cap, kEmptyKey, s);
-  if (e == hipSuccess) e = launch_fill_u64(vals, (int64_t)cap, 0, s);
+                              const int32_t* tail, uint64_t* table, uint64_t cap, uint32_t* overflow, hipStream_t s) {
+  const int64_t fb = (int64_t)((cap + 255) / 256);
+  k_fill_table<<<(unsigned)(fb < 8192 ? fb : 8192), 256, 0, s>>>(table, (int64_t)cap);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ntiles == 0) return e;
-  k_seq_windows<<<(unsigned)g.ntiles, kTileThreads, 0, s>>>(g, n, len, head, tail, keys, vals, cap - 1, overflow);
+  k_seq_windows<<<(unsigned)g.ntiles, kTileThreads, 0, s>>>(g, n, len, head, tail, table, cap - 1, overflow);
   return hipGetLastError();
 }
 
@@ -284,13 +293,13 @@ hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, c
 // Compaction of the occupied slots (any order: a radix sort follows). Slot
 // i0 + k * 256 + thread for k < 16: the lanes of a wave read consecutive
 // slots, one line per 8 lanes.
-__global__ __launch_bounds__(256) void k_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt) {
+__global__ __launch_bounds__(256) void k_occ_count(const uint64_t* table, int64_t cap, uint32_t* cnt) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t i = i0 + k * 256;
-    if (i < cap && __builtin_nontemporal_load(keys + i) != kEmptyKey) ++c;
+    if (i < cap && __builtin_nontemporal_load(table + 2 * i) != kEmptyKey) ++c;
   }
   __shared__ uint32_t lds[4];
   uint32_t total;
@@ -298,15 +307,15 @@ __global__ __launch_bounds__(256) void k_occ_count(const uint64_t* keys, int64_t
   if (threadIdx.x == 0) cnt[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(256) void k_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap,
-                                                   const uint32_t* off, uint64_t* okey, uint64_t* oval) {
+__global__ __launch_bounds__(256) void k_occ_write(const uint64_t* table, int64_t cap, const uint32_t* off,
+                                                   uint64_t* okey, uint64_t* oval) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
   uint64_t kv[16];
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t i = i0 + k * 256;
-    kv[k] = i < cap ? __builtin_nontemporal_load(keys + i) : kEmptyKey;
+    kv[k] = i < cap ? __builtin_nontemporal_load(table + 2 * i) : kEmptyKey;
     c += kv[k] != kEmptyKey;
   }
   __shared__ uint32_t lds[4];
@@ -316,24 +325,24 @@ __global__ __launch_bounds__(256) void k_occ_write(const uint64_t* keys, const u
   for (int k = 0; k < 16; ++k)
     if (kv[k] != kEmptyKey) {
       okey[pos] = kv[k];
-      oval[pos] = vals[i0 + k * 256];
+      oval[pos] = table[2 * (i0 + k * 256) + 1];
       ++pos;
     }
 }
 
-hipError_t launch_occ_count(const uint64_t* keys, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
+hipError_t launch_occ_count(const uint64_t* table, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
                             hipStream_t s) {
   const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
-  k_occ_count<<<(unsigned)nb, 256, 0, s>>>(keys, cap, cnt);
+  k_occ_count<<<(unsigned)nb, 256, 0, s>>>(table, cap, cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_scan_u32(cnt, nb, total, sums, s);
 }
 
-hipError_t launch_occ_write(const uint64_t* keys, const uint64_t* vals, int64_t cap, const uint32_t* off,
-                            uint64_t* okey, uint64_t* oval, hipStream_t s) {
+hipError_t launch_occ_write(const uint64_t* table, int64_t cap, const uint32_t* off, uint64_t* okey, uint64_t* oval,
+                            hipStream_t s) {
   const int64_t nb = (cap + kRadixTile - 1) / kRadixTile;
-  k_occ_write<<<(unsigned)nb, 256, 0, s>>>(keys, vals, cap, off, okey, oval);
+  k_occ_write<<<(unsigned)nb, 256, 0, s>>>(table, cap, off, okey, oval);
   return hipGetLastError();
 }
 
