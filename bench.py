@@ -366,7 +366,7 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
+        print(json.dumps({"error": "one GPU only: the multi-GPU path (sharding by symbol range or files) is not implemented"}))
         sys.exit(2)
     if args.copy_calibration:
         import torch
