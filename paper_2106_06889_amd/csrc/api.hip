@@ -453,7 +453,9 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   }
   if (!hip_ok(gt::launch_level_frontier(d, pend, lc, sums, s), "levels"))
     return bail(GTADOC_ERR_HIP);
-  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);
+  if (!hip_ok(gt::prepare_level_walk(d, pend, lc, sums, wide, s), "levels"))
+    return bail(GTADOC_ERR_HIP);
+  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);  // the level walk kernel alone
   if (!hip_ok(gt::launch_level_walk(d, pend, level_cnt, lc, sums, wide, ctx->device, s), "levels"))
     return bail(GTADOC_ERR_HIP);
   t_levels.end();

@@ -123,6 +123,8 @@ hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entri
 // level 1 (rules no rule references) by compaction, then the level walk
 hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
                                  hipStream_t s);
+hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
+                              const WideBufs& wide, hipStream_t s);
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
                              uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s);
 

@@ -363,6 +363,17 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
     __syncthreads();
     const uint32_t s0 = L.seg[0], s1 = L.seg[1];
     if (s0 != s1) {
+      // the bucket's weights and pending counts are loaded before the entries
+      // are summed, so the flush does not wait for them
+      constexpr int kPer = kWideBucket / kLevelThreads;
+      uint64_t wpre[kPer];
+      int32_t ppre[kPer];
+#pragma unroll
+      for (int x = 0; x < kPer; ++x) {
+        const int32_t c = b * kWideBucket + (int32_t)threadIdx.x + x * kLevelThreads;
+        wpre[x] = c < g.R ? g.w[c] : 0;
+        ppre[x] = c < g.R ? pend[c] : 0;
+      }
       for (int k = threadIdx.x; k < kWideBucket; k += blockDim.x) L.u.dense.wsum[k] = 0, L.u.dense.cnt[k] = 0;
       __syncthreads();
       for (uint32_t e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
@@ -372,13 +383,15 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
         atomicAdd(&L.u.dense.cnt[k], 1u);
       }
       __syncthreads();
-      for (int k = threadIdx.x; k < kWideBucket; k += blockDim.x) {
+#pragma unroll
+      for (int x = 0; x < kPer; ++x) {
+        const int k = (int)threadIdx.x + x * kLevelThreads;
         const uint32_t n = L.u.dense.cnt[k];
         const int32_t c = b * kWideBucket + k;
         bool ready = false;
         if (n) {
-          g.w[c] += L.u.dense.wsum[k];
-          const int32_t left = pend[c] - (int32_t)n;
+          g.w[c] = wpre[x] + L.u.dense.wsum[k];
+          const int32_t left = ppre[x] - (int32_t)n;
           pend[c] = left;
           ready = left == 0;
         }
@@ -508,10 +521,15 @@ __global__ __launch_bounds__(256) void k_wide_caps(const int32_t* pend, int64_t 
   if (threadIdx.x == 0) cap[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
-                             uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s) {
+// The barrier words of the shrinking phase: 2 words after the frontier scan's scratch.
+static uint32_t* level_barrier_words(const DevGrammar& g, uint32_t* scratch) {
   const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
-  WideBufs wb = wide;
+  return scratch + nb + scan_sums_entries(nb);
+}
+
+hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
+                              const WideBufs& wide, hipStream_t s) {
+  const WideBufs& wb = wide;
   if (wb.ew) {
     // bucket regions: exclusive scan of the capacities; both cursors start there
     k_wide_caps<<<(unsigned)wb.nbk, 256, 0, s>>>(pend, g.R, wb.cur);
@@ -521,6 +539,12 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_
       e0 = hipMemcpyAsync(wb.seg_lo, wb.cur, sizeof(uint32_t) * wb.nbk, hipMemcpyDeviceToDevice, s);
     if (e0 != hipSuccess) return e0;
   }
+  return launch_fill_i32(reinterpret_cast<int32_t*>(level_barrier_words(g, scratch)), 2, 0, s);
+}
+
+hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
+                             uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s) {
+  WideBufs wb = wide;
   int per_cu = 0, cus = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), kLevelThreads, 0);
   if (e != hipSuccess) return e;
@@ -531,9 +555,7 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_
   const int64_t cap = cus;  // one workgroup per CU: few participants in every grid barrier
   const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
   DevGrammar gg = g;
-  uint32_t* bar = scratch + nb + scan_sums_entries(nb);  // 2 words after the frontier scan's scratch
-  e = launch_fill_i32(reinterpret_cast<int32_t*>(bar), 2, 0, s);
-  if (e != hipSuccess) return e;
+  uint32_t* bar = level_barrier_words(g, scratch);
   void* args[] = {&gg, &pend, &level_cnt, &lc, &wb, &bar};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(kLevelThreads), args, 0,
                                     s);
