@@ -100,7 +100,7 @@ struct LevelLds {
     uint32_t hist[kWideMaxBuckets];  // bucketed mode, scatter: per-bucket counts, then write cursors
   } u;
   int32_t longs[kLongList];  // rules with long bodies, walked by whole waves
-  int32_t list_n, list_base, nlong;
+  int32_t list_n, list_base, list_total, nlong;
   uint32_t seg[2];
   uint64_t part[kLevelThreads / 64];
 };
@@ -180,7 +180,12 @@ __device__ __forceinline__ void mid_barrier(uint32_t* bar, uint32_t& gen) {
 __device__ __forceinline__ void level_list_out(DevGrammar& g, int32_t* level_cnt, LevelLds& L, int32_t d, int32_t hi) {
   __syncthreads();
   const int32_t n_local = L.list_n < kLevelList ? L.list_n : kLevelList;
-  if (threadIdx.x == 0) L.list_base = n_local ? atomicAdd(&level_cnt[d + 1], n_local) : 0;
+  if (threadIdx.x == 0) {
+    L.list_base = n_local ? atomicAdd(&level_cnt[d + 1], n_local) : 0;
+    // the level's size when this workgroup is the only one appending (its
+    // spills, if any, were counted before this add)
+    L.list_total = n_local ? L.list_base + n_local : 0;
+  }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < n_local; k += blockDim.x) g.level_rule[hi + L.list_base + k] = L.list[k];
   if (threadIdx.x == 0) L.list_n = 0;
@@ -406,7 +411,7 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
 
 // Levels narrower than this finish on workgroup 0 alone (block barriers
 // instead of grid barriers); the other workgroups leave.
-constexpr int32_t kTailRules = 4 * kLevelThreads;
+constexpr int32_t kTailRules = kLevelThreads;
 
 __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt,
                                                           LoadCounters* lc, WideBufs wb, uint32_t* bar) {
@@ -468,7 +473,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
       level_round(g, pend, level_cnt, L, lo, hi, d, threadIdx.x, blockDim.x, tokens);
       __threadfence();
       __syncthreads();
-      const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t next = L.list_total;
       if (threadIdx.x == 0) {
         g.level_off[d] = lo;
         g.level_off[d + 1] = hi;
