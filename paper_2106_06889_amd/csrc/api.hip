@@ -93,6 +93,8 @@ class Arena {
 };
 
 constexpr size_t kPinnedBytes = 64 * 1024;
+constexpr size_t kPinnedLevelAt = 1024;  // byte offset of the level offsets read back at load
+constexpr int64_t kPinnedLevels = 4096;   // level offsets read back with the load counters
 
 }  // namespace
 
@@ -460,7 +462,12 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     return bail(GTADOC_ERR_HIP);
   t_levels.end();
   t_load.end();
+  // the counters and the first level offsets come back with one wait
+  static_assert(sizeof(gt::LoadCounters) <= kPinnedLevelAt, "counters overlap the level offsets");
+  int32_t* plevel = reinterpret_cast<int32_t*>(ctx->pinned + kPinnedLevelAt);
+  const int64_t nlev = std::min<int64_t>(R + 2, kPinnedLevels);
   if (!hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
+      !hip_ok(hipMemcpyAsync(plevel, d.level_off, sizeof(int32_t) * nlev, hipMemcpyDeviceToHost, s), "read levels") ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
   if (pc->status)
@@ -475,7 +482,9 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
                      (long long)(R - 1)));
   const int32_t D = pc->depth;
   g->level_off.assign((size_t)D + 2, 0);
-  if (D > 0) {
+  if (D > 0 && D + 2 <= nlev) {
+    std::copy(plevel, plevel + D + 2, g->level_off.begin());
+  } else if (D > 0) {
     if (!hip_ok(hipMemcpyAsync(g->level_off.data(), d.level_off, sizeof(int32_t) * (D + 2), hipMemcpyDeviceToHost, s),
                 "read levels") ||
         !hip_ok(hipStreamSynchronize(s), "sync"))

@@ -190,3 +190,41 @@ def test_vocabulary_beyond_bucket_table(ctx):
     tok = rng.choice(np.array([0, 7, V - 1, 1 << 20, (1 << 24) + 1], np.int64), size=3000).astype(np.int32)
     g = synth.compress(tok, np.array([0, 1000, 3000], np.int64), V)
     check_wc_sort(ctx, g, expect_tokens=3000)
+
+
+def test_deep_chain(ctx):
+    """A chain of 5,000 rules under the root: one rule per level, a depth
+    past the level offsets read back together with the load counters, so the
+    longer read-back is taken; word count, sort, term vector, inverted index
+    and bigram/trigram counts against the oracle."""
+    import paper_2106_06889_amd as gt
+    R, V = 5001, 7
+    bodies = [np.array([-1, 3, -1, 4], np.int32)]  # root: rule 1 twice
+    bodies += [np.array([-(r + 1), r % V], np.int32) for r in range(1, R - 1)]
+    bodies.append(np.array([5, 6], np.int32))
+    rule_off = np.cumsum([0] + [len(b) for b in bodies]).astype(np.int64)
+    g = synth.Grammar(rule_off, np.concatenate(bodies), np.array([0, 2, 4], np.int64), V)
+    assert oracle.check_structure(g) == 0
+    st = check_wc_sort(ctx, g, expect_tokens=2 * R + 2)
+    assert st["depth"] == R - 1
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        tv = G.term_vector()
+        woff, wword, wcnt = oracle.traverse_term_vector(g)
+        assert np.array_equal(tv.arrays[0].cpu().numpy(), woff)
+        assert np.array_equal(tv.arrays[1].cpu().numpy().view(np.uint32), wword)
+        assert np.array_equal(gt.to_u64(tv.arrays[2]), wcnt)
+        ii = G.inverted_index_from(tv)
+        ioff, ifile = oracle.inverted_index(woff, wword, g.vocab)
+        assert np.array_equal(ii.arrays[0].cpu().numpy(), ioff)
+        assert np.array_equal(ii.arrays[1].cpu().numpy().view(np.uint32), ifile)
+        ii.free()
+        tv.free()
+        for n in (2, 3):
+            res = G.sequence_count(n)
+            wk, wc = oracle.traverse_sequence_count(g, n)
+            assert np.array_equal(gt.to_u64(res.arrays[0]), wk), n
+            assert np.array_equal(gt.to_u64(res.arrays[1]), wc), n
+            res.free()
+    finally:
+        G.free()
