@@ -25,13 +25,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-DEFAULT_WORKLOAD = {"wc": "wc-100m", "sc": "seq-20m", "tv": "tv-4000files"}
+DEFAULT_WORKLOAD = {"wc": "wc-100m", "sc": "seq-20m", "tv": "tv-4000files", "rii": "tv-4000files"}
 METRIC = {"wc": "uncompressed words/s analysed (word count)",
           "sc": "uncompressed words/s analysed (sequence count, n = 2 and 3)",
-          "tv": "uncompressed words/s analysed (term vector + inverted index)"}
+          "tv": "uncompressed words/s analysed (term vector + inverted index)",
+          "rii": "uncompressed words/s analysed (term vector + ranked inverted index)"}
 STEP = {"wc": "load (validate, levels, weights) + word count + sort",
         "sc": "load + sequence count n=2 + sequence count n=3",
-        "tv": "load + term vector + inverted index"}
+        "tv": "load + term vector + inverted index",
+        "rii": "load + term vector + ranked inverted index"}
 
 
 def log(msg: str):
@@ -58,17 +60,21 @@ def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
     import synth
     T = int(file_tokens.sum())
     t0 = time.perf_counter()
-    if query == "tv":
+    if query in ("tv", "rii"):
         F = g.num_files
         f, chunk = 0, max(1, F // 400)
         while f < F and time.perf_counter() - t0 < budget_s:
             hi = min(F, f + chunk)
-            oracle.traverse_term_vector(synth.Grammar(g.rule_off, g.sym, g.file_off[f:hi + 1], g.vocab))
+            off, word, cnt = oracle.traverse_term_vector(synth.Grammar(g.rule_off, g.sym, g.file_off[f:hi + 1],
+                                                                       g.vocab))
+            if query == "rii":
+                oracle.ranked_inverted_index(off, word, cnt, g.vocab)
             f = hi
         el = time.perf_counter() - t0
         toks = int(file_tokens[:f].sum())
+        what = "term vector" + (" + ranked inverted index of each chunk" if query == "rii" else "")
         return {"value": toks / el, "unit": "words/s", "cores": 1, "kind": "oracle",
-                "sample": f"per-file top-down traversal term vector of the first {f} of {F} files "
+                "sample": f"per-file top-down traversal {what}, first {f} of {F} files "
                           f"({toks} tokens) in {el:.1f} s"}
     reps = 0
     while True:
@@ -151,8 +157,10 @@ def run_query(args):
     if q == "sc":
         # exact table (16 B per slot, slots < 4 (n-1) S), results, sort scratch, head/tail/len
         arena += 256 * S + 48 * R
-    if q == "tv":
+    if q in ("tv", "rii"):
         arena += 48 * T // 10 + 64 * S + 64 * R + 16 * V + (1 << 30)
+    if q == "rii":
+        arena += 8 * T // 3  # term frequencies of the ranked index, 8 B per (file, word) pair
     ctx = gt.Context(arena, dev)
     counts = torch.empty(V, dtype=torch.int64, device=dev)
     ids = torch.empty(V, dtype=torch.int32, device=dev)
@@ -177,7 +185,7 @@ def run_query(args):
         else:
             tv = G.term_vector()
             sizes["nnz_tv"] = tv.length(1)
-            ii = G.inverted_index_from(tv)
+            ii = G.ranked_inverted_index_from(tv) if q == "rii" else G.inverted_index_from(tv)
             sizes["nnz_ii"] = ii.length(1)
             ii.free()
             tv.free()
@@ -242,7 +250,7 @@ def run_query(args):
         U = sizes.get("U2", 0) + sizes.get("U3", 0)
         cands["seq_windows"] = ("owned windows into the exact table (k_seq_windows)",
                                 (2 * (4 * S + 8 * (R + 1) + 16 * R) + 8 * R + 16 * R + 16 * U) / 2)
-    if q == "tv" and "tv_tables" in phases and "tv_reduce" in phases:
+    if q in ("tv", "rii") and "tv_tables" in phases and "tv_reduce" in phases:
         # the term vector pass (bottom-up tables + per-file reduce), per call
         phases["term_vector"] = {"avg_us": phases["tv_tables"]["avg_us"] + phases["tv_reduce"]["avg_us"],
                                  "count": phases["tv_tables"]["count"]}
@@ -353,7 +361,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--query", choices=("wc", "sc", "tv", "serve"), default="wc")
+    ap.add_argument("--query", choices=("wc", "sc", "tv", "rii", "serve"), default="wc")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")

@@ -161,6 +161,21 @@ int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream);
  * of g), OOM, HIP. */
 int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out, void* stream);
 
+/* Ranked inverted index (Section "Implementation": one of the six
+ * applications behind the CompressDirect interfaces; the paper names it
+ * without stating its order).
+ * Read here as: for every word, the files that contain it ordered by term
+ * frequency descending, ties by file ascending. Result arrays: [0] int64
+ * off[V+1], [1] uint32 file[NNZ], [2] uint64 tf[NNZ] (occurrences of the
+ * word in that file). Synchronizes `stream`. Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_ranked_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream);
+
+/* The ranked inverted index from a term vector result of the same grammar
+ * (as gtadoc_inverted_index_from_tv). Errors: INVALID_ARG (null, or a result
+ * that is not a term vector of g), OOM, HIP. */
+int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out,
+                                         void* stream);
+
 /* Sequence count (Section "Sequence Support"): occurrences of every run of n
  * consecutive words inside one file (runs never cross files), n in {2, 3}.
  * Result arrays: [0] uint64 key[U] ascending, [1] uint64 count[U], where the

@@ -15,6 +15,8 @@ All results are exact integers in canonical (sorted) order:
   sort            (uint32 id[K], uint64 cnt[K]) by count desc, id asc
   term_vector     (int64 off[F+1], uint32 word[NNZ], uint64 cnt[NNZ]) per file, word asc
   inverted_index  (int64 off[V+1], uint32 file[NNZ]) per word, file asc
+  ranked_inverted_index  (int64 off[V+1], uint32 file[NNZ], uint64 tf[NNZ]) per
+                  word, tf desc, then file asc
   sequence_count  (uint64 key[U], uint64 cnt[U]) key asc; key packs the n-gram
                   (n=2: w0<<32|w1; n=3: w0<<42|w1<<21|w2)
 """
@@ -184,6 +186,28 @@ def inverted_index(tv_off: np.ndarray, tv_word: np.ndarray, vocab: int):
            "inverted_index")
     off = _take(po, vocab + 1, np.int64)
     return off, _take(pf, int(off[-1]), np.uint32)
+
+
+def ranked_inverted_index(tv_off: np.ndarray, tv_word: np.ndarray, tv_cnt: np.ndarray, vocab: int):
+    """Ranked inverted index from a term vector (the paper lists it among the
+    applications of its Implementation section without stating its order).
+    Reading: for every word, the files that contain it, ordered by the word's
+    occurrences in the file (term frequency) descending, ties by file id
+    ascending. Returns (int64 off[V+1], uint32 file[NNZ], uint64 tf[NNZ]).
+    A library sort is the one step: keys (word asc, tf desc, file asc)."""
+    tv_off = np.asarray(tv_off, dtype=np.int64)
+    word = np.asarray(tv_word, dtype=np.int64)
+    tf = np.asarray(tv_cnt, dtype=np.uint64)
+    file = np.repeat(np.arange(len(tv_off) - 1, dtype=np.int64), np.diff(tv_off))
+    order = np.lexsort((file, -tf.astype(np.int64), word))
+    off = np.zeros(vocab + 1, np.int64)
+    np.cumsum(np.bincount(word, minlength=vocab), out=off[1:])
+    return off, file[order].astype(np.uint32), tf[order]
+
+
+def ranked_inverted_index_of(g):
+    off, word, cnt = traverse_term_vector(g)
+    return ranked_inverted_index(off, word, cnt, int(g.vocab))
 
 
 def sc_text(tokens: np.ndarray, file_off: np.ndarray, n: int, vocab: int):

@@ -750,7 +750,7 @@ int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
 
 namespace {
 // Inverted index of g from its term vector `a`, into a new result.
-int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, gtadoc_result* out) {
+int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, bool ranked, gtadoc_result* out) {
   hipStream_t s = call.stream();
   const int64_t NNZ = a.nnz;
   const int32_t V = g->d.V;
@@ -758,6 +758,7 @@ int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, gtadoc_
   if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
   auto* ii_off = call.keep<int64_t>((int64_t)V + 1, res->blocks);
   auto* file = call.keep<uint32_t>(NNZ, res->blocks);
+  auto* tf = ranked ? call.keep<uint64_t>(NNZ, res->blocks) : nullptr;
   auto* k0 = call.scratch<uint64_t>(NNZ);
   auto* k1 = call.scratch<uint64_t>(NNZ);
   auto* kout = call.scratch<uint64_t>(NNZ);
@@ -765,15 +766,16 @@ int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, gtadoc_
   auto* v1 = call.scratch<uint32_t>(NNZ);
   auto* hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(NNZ));
   auto* num = call.scratch<int64_t>(1);
-  if (!ii_off || !file || !k0 || !k1 || !kout || !v0 || !v1 || !hist || !num) {
+  if (!ii_off || !file || (ranked && !tf) || !k0 || !k1 || !kout || !v0 || !v1 || !hist || !num) {
     (void)hipStreamSynchronize(s);
     release_all(g->ctx, res->blocks);
     delete res;
-    return oom("inverted index", 40ull * NNZ);
+    return oom("inverted index", 48ull * NNZ);
   }
   hipError_t e = gt::launch_fill_u64(reinterpret_cast<uint64_t*>(num), 1, (uint64_t)NNZ, s);
   if (e == hipSuccess)
-    e = gt::launch_ii(a.off, g->d.F, a.word, NNZ, V, k0, v0, k1, v1, kout, file, num, hist, ii_off, s);
+    e = gt::launch_ii(a.off, g->d.F, a.word, ranked ? a.cnt : nullptr, NNZ, V, k0, v0, k1, v1, kout, file, num, hist,
+                      ii_off, tf, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);
@@ -784,12 +786,12 @@ int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, gtadoc_
   res->a[0] = {ii_off, (int64_t)V + 1, 8};
   res->a[1] = {file, NNZ, 4};
   res->na = 2;
+  if (ranked) res->a[2] = {tf, NNZ, 8}, res->na = 3;
   *out = res;
   return GTADOC_OK;
 }
-}  // namespace
 
-int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+int inverted_index_entry(gtadoc_grammar g, bool ranked, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   Call call(g->ctx, stream);
   int rc = call.begin();
@@ -797,10 +799,11 @@ int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
   TvArrays a;
   rc = term_vector_into(g, call, nullptr, &a);
   if (rc) return rc;
-  return inverted_index_from(g, call, a, out);
+  return inverted_index_from(g, call, a, ranked, out);
 }
 
-int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out, void* stream) {
+int inverted_index_from_tv_entry(gtadoc_grammar g, gtadoc_result term_vector, bool ranked, gtadoc_result* out,
+                                 void* stream) {
   if (!g || !term_vector || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   if (term_vector->tv_of != g) return fail(GTADOC_ERR_INVALID_ARG, "not a term vector result of this grammar");
   Call call(g->ctx, stream);
@@ -811,7 +814,25 @@ int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, g
   a.word = static_cast<uint32_t*>(term_vector->a[1].p);
   a.cnt = static_cast<uint64_t*>(term_vector->a[2].p);
   a.nnz = term_vector->a[1].n;
-  return inverted_index_from(g, call, a, out);
+  return inverted_index_from(g, call, a, ranked, out);
+}
+}  // namespace
+
+int gtadoc_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  return inverted_index_entry(g, false, out, stream);
+}
+
+int gtadoc_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out, void* stream) {
+  return inverted_index_from_tv_entry(g, term_vector, false, out, stream);
+}
+
+int gtadoc_ranked_inverted_index(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  return inverted_index_entry(g, true, out, stream);
+}
+
+int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_vector, gtadoc_result* out,
+                                         void* stream) {
+  return inverted_index_from_tv_entry(g, term_vector, true, out, stream);
 }
 
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {

@@ -187,9 +187,13 @@ hipError_t launch_tv_reduce(const DevGrammar& g, const TvFiles& t, uint64_t* ent
 hipError_t launch_tv_emit(const DevGrammar& g, const TvFiles& t, const uint64_t* entries, int64_t E,
                           const uint32_t* nnz, const uint32_t* noff, uint32_t* out_word, uint64_t* out_cnt,
                           int64_t* out_off, hipStream_t s);
-hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, int64_t nnz, int32_t V,
-                     uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout, uint32_t* file_out,
-                     const int64_t* num, uint32_t* hist, int64_t* ii_off, hipStream_t s);
+// Inverted index from a term vector (file-major, words ascending per file).
+// With tv_cnt set, the ranked index: per word by term frequency descending,
+// then file ascending, term frequencies in tf_out.
+hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, const uint64_t* tv_cnt, int64_t nnz,
+                     int32_t V, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout,
+                     uint32_t* file_out, const int64_t* num, uint32_t* hist, int64_t* ii_off, uint64_t* tf_out,
+                     hipStream_t s);
 hipError_t launch_scan_u64_ext(uint64_t* a, int64_t n, int64_t* total, uint64_t* sums, hipStream_t s);
 hipError_t launch_scan_u32_ext(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
 

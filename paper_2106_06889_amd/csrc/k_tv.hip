@@ -840,8 +840,12 @@ hipError_t launch_tv_emit(const DevGrammar& g, const TvFiles& t, const uint64_t*
 // entries: the files of its first and last entry are found once (binary
 // search on tv_off), and each entry searches only that range (nearly always
 // one file), instead of a full search per entry.
+// One (key, file) pair per term-vector entry, in the term vector's
+// file-major order. key = word, or for the ranked index (tv_cnt given)
+// word << 32 | (2^32 - 1 - tf), so that one ascending stable sort orders by
+// word, then term frequency descending, then file (the input order).
 __global__ __launch_bounds__(256) void k_ii_pairs(const int64_t* tv_off, int64_t F, const uint32_t* tv_word,
-                                                  int64_t nnz, uint64_t* key, uint32_t* file) {
+                                                  const uint64_t* tv_cnt, int64_t nnz, uint64_t* key, uint32_t* file) {
   __shared__ int64_t frange[2];
   const int64_t c0 = (int64_t)blockIdx.x * 4096;
   const int64_t c1 = c0 + 4096 < nnz ? c0 + 4096 : nnz;
@@ -864,33 +868,48 @@ __global__ __launch_bounds__(256) void k_ii_pairs(const int64_t* tv_off, int64_t
       if (tv_off[mid] <= i) lo = mid;
       else hi = mid - 1;
     }
-    key[i] = tv_word[i];
+    key[i] = tv_cnt ? (uint64_t)tv_word[i] << 32 | (0xffffffffull - tv_cnt[i]) : (uint64_t)tv_word[i];
     file[i] = (uint32_t)lo;
   }
 }
 
-__global__ void k_ii_offsets(const uint64_t* key, int64_t nnz, int32_t V, int64_t* off) {
+__global__ void k_ii_offsets(const uint64_t* key, int shift, int64_t nnz, int32_t V, int64_t* off) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i > nnz) return;
-  // words w in (key[i-1], key[i]] start at i; past the end, up to V
-  const int64_t prev = i == 0 ? -1 : (int64_t)key[i - 1];
-  const int64_t cur = i == nnz ? (int64_t)V : (int64_t)key[i];
+  // words w in (word[i-1], word[i]] start at i; past the end, up to V
+  const int64_t prev = i == 0 ? -1 : (int64_t)(key[i - 1] >> shift);
+  const int64_t cur = i == nnz ? (int64_t)V : (int64_t)(key[i] >> shift);
   for (int64_t w = prev + 1; w <= cur; ++w) off[w] = i;
 }
 
-hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, int64_t nnz, int32_t V,
-                     uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout, uint32_t* file_out,
-                     const int64_t* num, uint32_t* hist, int64_t* ii_off, hipStream_t s) {
+// Term frequencies of the ranked index, back from the sorted keys.
+__global__ void k_rii_tf(const uint64_t* key, int64_t nnz, uint64_t* tf) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < nnz) tf[i] = 0xffffffffull - (key[i] & 0xffffffffull);
+}
+
+hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, const uint64_t* tv_cnt, int64_t nnz,
+                     int32_t V, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t* kout,
+                     uint32_t* file_out, const int64_t* num, uint32_t* hist, int64_t* ii_off, uint64_t* tf_out,
+                     hipStream_t s) {
+  const int shift = tv_cnt ? 32 : 0;
   if (nnz > 0) {
-    k_ii_pairs<<<(unsigned)((nnz + 4095) / 4096), 256, 0, s>>>(tv_off, F, tv_word, nnz, k0, v0);
+    k_ii_pairs<<<(unsigned)((nnz + 4095) / 4096), 256, 0, s>>>(tv_off, F, tv_word, tv_cnt, nnz, k0, v0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int b = 1;
     while (b < 32 && (1ll << b) < (int64_t)V) ++b;
-    e = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, num, nnz, 0, b, false, hist, kout, file_out, s);
+    // word bytes, and for the ranked index the four frequency bytes below them
+    e = radix_sort_pairs<uint32_t>(k0, v0, k1, v1, num, nnz, tv_cnt ? 0 : shift, shift + b, false, hist, kout,
+                                   file_out, s);
     if (e != hipSuccess) return e;
+    if (tv_cnt) {
+      k_rii_tf<<<(unsigned)((nnz + 255) / 256), 256, 0, s>>>(kout, nnz, tf_out);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
-  k_ii_offsets<<<(unsigned)((nnz + 1 + 255) / 256), 256, 0, s>>>(kout, nnz, V, ii_off);
+  k_ii_offsets<<<(unsigned)((nnz + 1 + 255) / 256), 256, 0, s>>>(kout, shift, nnz, V, ii_off);
   return hipGetLastError();
 }
 

@@ -57,6 +57,8 @@ EXPORTS = {
     "gtadoc_term_vector": [_vp, _vp, _vp],
     "gtadoc_inverted_index": [_vp, _vp, _vp],
     "gtadoc_inverted_index_from_tv": [_vp, _vp, _vp, _vp],
+    "gtadoc_ranked_inverted_index": [_vp, _vp, _vp],
+    "gtadoc_ranked_inverted_index_from_tv": [_vp, _vp, _vp, _vp],
     "gtadoc_sequence_count": [_vp, _int, _vp, _vp],
     "gtadoc_result_array": [_vp, _int, _vp, _vp, _vp],
     "gtadoc_result_free": [_vp],
@@ -258,6 +260,15 @@ class Grammar:
     def inverted_index_from(self, term_vector: "Result", stream=None) -> Result:
         """Inverted index from this grammar's term vector result (no recomputation)."""
         return self._result(lib().gtadoc_inverted_index_from_tv, term_vector.handle, stream=stream)
+
+    def ranked_inverted_index(self, stream=None) -> Result:
+        """Per word, the files containing it by term frequency descending, then
+        file ascending: arrays (off int64[V+1], file int32[NNZ], tf int64[NNZ])."""
+        return self._result(lib().gtadoc_ranked_inverted_index, stream=stream)
+
+    def ranked_inverted_index_from(self, term_vector: "Result", stream=None) -> Result:
+        """The ranked inverted index from a term vector result of this grammar."""
+        return self._result(lib().gtadoc_ranked_inverted_index_from_tv, term_vector.handle, stream=stream)
 
     def sequence_count(self, n: int, stream=None) -> Result:
         return self._result(lib().gtadoc_sequence_count, n, stream=stream)

@@ -1,8 +1,9 @@
 """GPU parity at the full workload sizes (complete outputs against the
 oracle's traversal, which is fast in C): word count + sort on the 100M-token
 single-file corpus, bigram and trigram counts on the 20M-token nested-repeat
-corpus; term vector + inverted index on the 4,000-file corpus (sampled files
-against the uncompressed text, properties on every file)."""
+corpus; term vector + inverted index + ranked inverted index on the
+4,000-file corpus (sampled files against the uncompressed text, properties
+on every file)."""
 import numpy as np
 import pytest
 
@@ -87,6 +88,11 @@ def test_tv_4000files_full(capsys):
         ioff = ii.arrays[0].cpu().numpy()
         ifile = ii.arrays[1].cpu().numpy().view(np.uint32).astype(np.int64)
         ii.free()
+        rii = G.ranked_inverted_index_from(tv)
+        roff = rii.arrays[0].cpu().numpy()
+        rfile = rii.arrays[1].cpu().numpy().view(np.uint32).astype(np.int64)
+        rtf = gt.to_u64(rii.arrays[2])
+        rii.free()
         tv.free()
         G.free()
     finally:
@@ -119,3 +125,8 @@ def test_tv_4000files_full(capsys):
     want_off = np.concatenate([[0], np.cumsum(np.bincount(word, minlength=V))])
     assert np.array_equal(ioff[:V + 1], want_off)
     assert np.array_equal(ifile[:nnz], file_of[order])
+    # the ranked index: per word, term frequency desc, then file asc
+    rorder = np.lexsort((file_of, -cnt.astype(np.int64), word))
+    assert np.array_equal(roff[:V + 1], want_off)
+    assert np.array_equal(rfile[:nnz], file_of[rorder])
+    assert np.array_equal(rtf[:nnz], cnt[rorder])

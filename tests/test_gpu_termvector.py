@@ -41,6 +41,17 @@ def gpu_ii(G):
     return off, files
 
 
+def gpu_rii(res):
+    import paper_2106_06889_amd as gt
+    out = (res.arrays[0].cpu().numpy(), res.arrays[1].cpu().numpy().view(np.uint32), gt.to_u64(res.arrays[2]))
+    res.free()
+    return out
+
+
+def same_rii(got, want):
+    return all(np.array_equal(a, b) for a, b in zip(got, want))
+
+
 def check(ctx, g, brute=True):
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
     try:
@@ -61,7 +72,11 @@ def check(ctx, g, brute=True):
         assert np.array_equal(ii.arrays[0].cpu().numpy(), woff2)
         assert np.array_equal(ii.arrays[1].cpu().numpy().view(np.uint32), wfile)
         ii.free()
+        # ranked: files by term frequency desc, then file asc
+        want_r = oracle.ranked_inverted_index(woff, wword, wcnt, g.vocab)
+        assert same_rii(gpu_rii(G.ranked_inverted_index_from(tv)), want_r)
         tv.free()
+        assert same_rii(gpu_rii(G.ranked_inverted_index()), want_r)
     finally:
         G.free()
 
@@ -146,12 +161,46 @@ def test_inverted_index_from_foreign_result(ctx):
         with pytest.raises(gt.GtadocError) as e:
             G.inverted_index_from(sc)
         assert e.value.code == gt.ERR_INVALID_ARG
+        with pytest.raises(gt.GtadocError) as e:
+            G.ranked_inverted_index_from(sc)
+        assert e.value.code == gt.ERR_INVALID_ARG
         tv = H.term_vector()
         with pytest.raises(gt.GtadocError) as e:
             G.inverted_index_from(tv)  # a term vector of another grammar
+        assert e.value.code == gt.ERR_INVALID_ARG
+        with pytest.raises(gt.GtadocError) as e:
+            G.ranked_inverted_index_from(tv)
         assert e.value.code == gt.ERR_INVALID_ARG
         tv.free()
         sc.free()
     finally:
         G.free()
         H.free()
+
+
+def test_golden_ranked_inverted_index(ctx):
+    with open(os.path.join(GOLD, "e4_ranked_inverted_index.json")) as f:
+        d = json.load(f)
+    tokens = np.concatenate([np.asarray(x, np.int32) for x in d["files"]])
+    file_off = np.concatenate([[0], np.cumsum([len(x) for x in d["files"]])]).astype(np.int64)
+    g = synth.compress(tokens, file_off, d["vocab"])
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        off, file, tf = gpu_rii(G.ranked_inverted_index())
+        want = d["ranked_inverted_index"]
+        assert off.tolist() == want["off"] and file.tolist() == want["file"] and tf.tolist() == want["tf"]
+    finally:
+        G.free()
+
+
+def test_ranked_ties_and_heavy_counts(ctx):
+    """Many files with equal term frequencies (ties broken by file id) and a
+    word whose frequency in one file needs more than 16 bits."""
+    rng = np.random.default_rng(9)
+    files = [np.array([1, 2, 1, 2, 3], np.int32) for _ in range(40)]
+    files.append(np.full(70000, 4, np.int32))
+    files.append(np.concatenate([np.full(65536, 4, np.int32), rng.integers(0, 6, 300).astype(np.int32)]))
+    tokens = np.concatenate(files)
+    file_off = np.concatenate([[0], np.cumsum([len(x) for x in files])]).astype(np.int64)
+    g = synth.compress(tokens, file_off, 6)
+    check(ctx, g, brute=False)

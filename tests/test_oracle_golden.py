@@ -130,3 +130,48 @@ def test_e4_root_only_reduces_to_textbook(seed):
             for i in range(len(t) - n + 1):
                 ctr[oracle.pack(t[i:i + n], n)] += 1
         assert as_dict(*oracle.traverse_sequence_count(g, n)) == dict(ctr)
+
+
+def _grammar_of_files(files, vocab):
+    tokens = np.concatenate([np.asarray(f, np.int32) for f in files])
+    file_off = np.concatenate([[0], np.cumsum([len(f) for f in files])]).astype(np.int64)
+    return tokens, file_off, synth.compress(tokens, file_off, vocab)
+
+
+def test_e4_ranked_inverted_index_hand_worked():
+    with open(os.path.join(GOLD, "e4_ranked_inverted_index.json")) as f:
+        d = json.load(f)
+    _, _, g = _grammar_of_files(d["files"], d["vocab"])
+    want = d["ranked_inverted_index"]
+    for off, word, cnt in (oracle.traverse_term_vector(g), oracle.brute_term_vector(g)):
+        roff, rfile, rtf = oracle.ranked_inverted_index(off, word, cnt, d["vocab"])
+        assert roff.tolist() == want["off"] and rfile.tolist() == want["file"] and rtf.tolist() == want["tf"]
+    roff, rfile, rtf = oracle.ranked_inverted_index_of(g)
+    assert rfile.tolist() == want["file"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ranked_inverted_index_by_counting(seed):
+    """Against a pure-Python construction from the text (a counter per file,
+    then each word's (file, tf) list sorted by tf desc, file asc), and the
+    plain inverted index's file sets."""
+    c = synth.random_corpus(300 + seed, 1 + 3 * (seed % 4), 1500, [5, 40, 300][seed % 3])
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    roff, rfile, rtf = oracle.ranked_inverted_index_of(g)
+    per_word = collections.defaultdict(list)
+    for f in range(len(c.file_off) - 1):
+        for w, k in collections.Counter(c.tokens[c.file_off[f]:c.file_off[f + 1]].tolist()).items():
+            per_word[w].append((f, k))
+    files, tfs, off = [], [], [0]
+    for w in range(c.vocab):
+        for f, k in sorted(per_word[w], key=lambda x: (-x[1], x[0])):
+            files.append(f)
+            tfs.append(k)
+        off.append(len(files))
+    assert roff.tolist() == off and rfile.tolist() == files and rtf.tolist() == tfs
+    ioff, ifile = oracle.inverted_index_of(g)
+    assert np.array_equal(ioff, roff)
+    for w in range(c.vocab):
+        assert sorted(rfile[roff[w]:roff[w + 1]].tolist()) == ifile[ioff[w]:ioff[w + 1]].tolist()
+    assert np.array_equal(np.add.reduceat(rtf, roff[:-1][np.diff(roff) > 0]) if len(rtf) else rtf,
+                          oracle.wc_text(c.tokens, c.vocab)[np.diff(roff) > 0])
