@@ -18,7 +18,7 @@ All results are exact integers in canonical (sorted) order:
   ranked_inverted_index  (int64 off[V+1], uint32 file[NNZ], uint64 tf[NNZ]) per
                   word, tf desc, then file asc
   sequence_count  (uint64 key[U], uint64 cnt[U]) key asc; key packs the n-gram
-                  (n=2: w0<<32|w1; n=3: w0<<42|w1<<21|w2)
+                  (n=2: w0<<32|w1; n=3: w0<<42|w1<<21|w2; n=4: 16 bits per word)
 """
 from __future__ import annotations
 
@@ -314,4 +314,6 @@ def pack(gram, n: int) -> int:
         return int(gram[0])
     if n == 2:
         return int(gram[0]) << 32 | int(gram[1])
-    return int(gram[0]) << 42 | int(gram[1]) << 21 | int(gram[2])
+    if n == 3:
+        return int(gram[0]) << 42 | int(gram[1]) << 21 | int(gram[2])
+    return int(gram[0]) << 48 | int(gram[1]) << 32 | int(gram[2]) << 16 | int(gram[3])

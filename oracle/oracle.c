@@ -23,7 +23,8 @@
  *
  * Sequence keys pack an n-gram (w0 .. w(n-1)) so that ascending keys are
  * lexicographic n-gram order:
- *   n = 1: w0;  n = 2: w0 << 32 | w1;  n = 3: w0 << 42 | w1 << 21 | w2 (V <= 2^21).
+ *   n = 1: w0;  n = 2: w0 << 32 | w1;  n = 3: w0 << 42 | w1 << 21 | w2 (V <= 2^21);
+ *   n = 4: w0 << 48 | w1 << 32 | w2 << 16 | w3 (V <= 2^16).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -303,7 +304,9 @@ static int cmp_u64(const void* a, const void* b) {
 static uint64_t pack_key(const int32_t* g, int n) {
   if (n == 1) return (uint64_t)(uint32_t)g[0];
   if (n == 2) return (uint64_t)(uint32_t)g[0] << 32 | (uint32_t)g[1];
-  return (uint64_t)(uint32_t)g[0] << 42 | (uint64_t)(uint32_t)g[1] << 21 | (uint32_t)g[2];
+  if (n == 3) return (uint64_t)(uint32_t)g[0] << 42 | (uint64_t)(uint32_t)g[1] << 21 | (uint32_t)g[2];
+  return (uint64_t)(uint32_t)g[0] << 48 | (uint64_t)(uint32_t)g[1] << 32 | (uint64_t)(uint32_t)g[2] << 16 |
+         (uint32_t)g[3];
 }
 
 /* Collapse a list of keys (ascending after sorting) into (key, count) runs.
@@ -336,7 +339,7 @@ static int64_t runs_of(uint64_t* keys, int64_t m, uint64_t** key_out, uint64_t**
  * count runs: no hashing. */
 int64_t or_sc_text(const int32_t* tok, const int64_t* file_off, int64_t F, int n, int32_t V,
                    uint64_t** key_out, uint64_t** cnt_out) {
-  if (n < 1 || n > 3 || (n == 3 && V > (1 << 21))) return OR_ERR_ARG;
+  if (n < 1 || n > 4 || (n == 3 && V > (1 << 21)) || (n == 4 && V > (1 << 16))) return OR_ERR_ARG;
   int64_t m = 0, T = file_off[F];
   uint64_t* keys = malloc(sizeof(uint64_t) * (size_t)(T > 0 ? T : 1));
   if (!keys) return OR_ERR_NOMEM;
@@ -662,7 +665,7 @@ static int64_t owned_windows(const int64_t* rule_off, const int32_t* sym, const 
  * of sequence support. own must hold R entries. */
 int or_owned_counts(const int64_t* rule_off, int64_t R, const int32_t* sym, const int64_t* file_off,
                     int64_t F, int n, uint64_t* own) {
-  if (n < 1 || n > 3) return OR_ERR_ARG;
+  if (n < 1 || n > 4) return OR_ERR_ARG;
   size_t hs = (size_t)R * (size_t)(n > 1 ? n - 1 : 1);
   uint64_t* len = malloc(sizeof(uint64_t) * (size_t)R);
   int32_t* head = malloc(sizeof(int32_t) * hs);
@@ -700,7 +703,7 @@ static int cmp_pair(const void* a, const void* b) {
  * pairs are merged by sorting, into ascending (key, count) pairs. */
 int64_t or_sc_traverse(const int64_t* rule_off, int64_t R, const int32_t* sym, const int64_t* file_off,
                        int64_t F, int n, int32_t V, uint64_t** key_out, uint64_t** cnt_out) {
-  if (n < 1 || n > 3 || (n == 3 && V > (1 << 21))) return OR_ERR_ARG;
+  if (n < 1 || n > 4 || (n == 3 && V > (1 << 21)) || (n == 4 && V > (1 << 16))) return OR_ERR_ARG;
   size_t hs = (size_t)R * (size_t)(n > 1 ? n - 1 : 1);
   uint64_t* len = malloc(sizeof(uint64_t) * (size_t)R);
   uint64_t* w = malloc(sizeof(uint64_t) * (size_t)R);

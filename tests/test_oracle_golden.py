@@ -123,7 +123,7 @@ def test_e4_root_only_reduces_to_textbook(seed):
         nz = np.nonzero(bc)[0]
         assert tw[toff[f]:toff[f + 1]].tolist() == nz.tolist()
         assert tc[toff[f]:toff[f + 1]].tolist() == bc[nz].tolist()
-    for n in (2, 3):
+    for n in (2, 3, 4):
         ctr = collections.Counter()
         for f in range(4):
             t = tok[off[f]:off[f + 1]].tolist()

@@ -54,13 +54,13 @@ def test_traversal_equals_brute_force(seed, files, max_tokens, vocab):
     # sequences, n = 1 reduces to the word count
     k1, c1 = oracle.traverse_sequence_count(g, 1)
     assert np.array_equal(k1, np.nonzero(wc)[0].astype(np.uint64)) and np.array_equal(c1, wc[wc > 0])
-    for n in (2, 3):
+    for n in (2, 3, 4):
         k, cn = oracle.traverse_sequence_count(g, n)
         bk, bc = oracle.sc_text(c.tokens, c.file_off, n, vocab)
         assert np.array_equal(k, bk) and np.array_equal(cn, bc)
         sizes = np.diff(c.file_off)
         assert int(cn.sum()) == int(np.maximum(sizes - n + 1, 0).sum())
-        assert np.all(np.diff(k.astype(np.float64)) > 0) if len(k) > 1 else True
+        assert np.all(k[1:] > k[:-1])  # strictly ascending (uint64 compare: n = 4 keys exceed 2^53)
 
 
 @pytest.mark.parametrize("seed,files,max_tokens,vocab", CASES[:12])
@@ -87,6 +87,13 @@ def test_owned_windows_equal_eq1(seed, files, max_tokens, vocab):
             root_total += max(words + (n - 1) * subs - (n - 1), 0)
         assert int(own[0]) == root_total
         assert lens[0] >= 0
+    # n = 4: Eq. upperLimit is only an upper bound once a child expands to
+    # fewer than n - 1 = 3 words (Sequitur children have at least 2)
+    own = oracle.owned_counts(g, 4)
+    for r in range(1, g.num_rules):
+        body = g.sym[g.rule_off[r]:g.rule_off[r + 1]]
+        words, subs = int((body >= 0).sum()), int((body < 0).sum())
+        assert int(own[r]) <= max(words + 3 * subs - 3, 0), r
 
 
 def test_sort_order_is_total():
