@@ -25,13 +25,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-DEFAULT_WORKLOAD = {"wc": "wc-100m", "sc": "seq-20m", "tv": "tv-4000files", "rii": "tv-4000files"}
+DEFAULT_WORKLOAD = {"wc": "wc-100m", "sc": "seq-20m", "sc4": "seq4-20m", "tv": "tv-4000files",
+                    "rii": "tv-4000files"}
+SEQ_NS = {"sc": (2, 3), "sc4": (4,)}
 METRIC = {"wc": "uncompressed words/s analysed (word count)",
           "sc": "uncompressed words/s analysed (sequence count, n = 2 and 3)",
+          "sc4": "uncompressed words/s analysed (sequence count, n = 4)",
           "tv": "uncompressed words/s analysed (term vector + inverted index)",
           "rii": "uncompressed words/s analysed (term vector + ranked inverted index)"}
 STEP = {"wc": "load (validate, levels, weights) + word count + sort",
         "sc": "load + sequence count n=2 + sequence count n=3",
+        "sc4": "load + sequence count n=4",
         "tv": "load + term vector + inverted index",
         "rii": "load + term vector + ranked inverted index"}
 
@@ -81,14 +85,14 @@ def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
         if query == "wc":
             oracle.traverse_word_count(g)
         else:
-            oracle.traverse_sequence_count(g, 2)
-            oracle.traverse_sequence_count(g, 3)
+            for n in SEQ_NS[query]:
+                oracle.traverse_sequence_count(g, n)
         reps += 1
         el = time.perf_counter() - t0
         if el > budget_s or reps >= 20:
             break
     per = el / reps
-    what = "word count" if query == "wc" else "sequence count n=2 and n=3"
+    what = "word count" if query == "wc" else "sequence count " + " and ".join(f"n={n}" for n in SEQ_NS[query])
     return {"value": T / per, "unit": "words/s", "cores": 1, "kind": "oracle",
             "sample": f"whole grammar, {reps} run(s) of the sequential traversal {what}, {per:.3f} s each"}
 
@@ -154,8 +158,8 @@ def run_query(args):
     root_syms = int(g.rule_off[1] - g.rule_off[0])
     q = args.query
     arena = 64 * R + 8 * S + 64 * V + (64 << 20)
-    if q == "sc":
-        # exact table (16 B per slot, slots < 4 (n-1) S), results, sort scratch, head/tail/len
+    if q in SEQ_NS:
+        # exact table (16 B per slot, slots < 2 (n-1) S + 2), results, sort scratch, head/tail/len
         arena += 256 * S + 48 * R
     if q in ("tv", "rii"):
         arena += 48 * T // 10 + 64 * S + 64 * R + 16 * V + (1 << 30)
@@ -177,8 +181,8 @@ def run_query(args):
             gt.gtadoc._check(lib.gtadoc_word_count(G.handle, counts.data_ptr(), sp))
             gt.gtadoc._check(lib.gtadoc_sort(G.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
                                              num.data_ptr(), sp))
-        elif q == "sc":
-            for n in (2, 3):
+        elif q in SEQ_NS:
+            for n in SEQ_NS[q]:
                 res = G.sequence_count(n)
                 sizes[f"U{n}"] = res.length(0)
                 res.free()
@@ -202,9 +206,9 @@ def run_query(args):
     if q == "wc":
         total = int(gt.to_u64(G.word_count()).sum())
         assert total == T, (total, T)
-    elif q == "sc":
+    elif q in SEQ_NS:
         lens = file_tokens
-        for n in (2, 3):
+        for n in SEQ_NS[q]:
             res = G.sequence_count(n)
             tot = int(gt.to_u64(res.arrays[1]).sum())
             res.free()
@@ -246,10 +250,11 @@ def run_query(args):
     lv_bytes = 4 * (S - root_syms) + 8 * (R + 1) + 8 * R + 4 * R
     cands = {"levels": ("level walk (k_levels)", lv_bytes),
              "word_count": ("word count pass (bucket scatter + reduce)", wc_bytes)}
-    if q == "sc":
-        U = sizes.get("U2", 0) + sizes.get("U3", 0)
+    if q in SEQ_NS:
+        ns = SEQ_NS[q]
+        U = sum(sizes.get(f"U{n}", 0) for n in ns)
         cands["seq_windows"] = ("owned windows into the exact table (k_seq_windows)",
-                                (2 * (4 * S + 8 * (R + 1) + 16 * R) + 8 * R + 16 * R + 16 * U) / 2)
+                                (len(ns) * (4 * S + 8 * (R + 1) + 16 * R) + 8 * R + 16 * R + 16 * U) / len(ns))
     if q in ("tv", "rii") and "tv_tables" in phases and "tv_reduce" in phases:
         # the term vector pass (bottom-up tables + per-file reduce), per call
         phases["term_vector"] = {"avg_us": phases["tv_tables"]["avg_us"] + phases["tv_reduce"]["avg_us"],
@@ -361,7 +366,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--query", choices=("wc", "sc", "tv", "rii", "serve"), default="wc")
+    ap.add_argument("--query", choices=("wc", "sc", "sc4", "tv", "rii", "serve"), default="wc")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")

@@ -177,12 +177,13 @@ int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_ve
                                          void* stream);
 
 /* Sequence count (Section "Sequence Support"): occurrences of every run of n
- * consecutive words inside one file (runs never cross files), n in {2, 3}.
+ * consecutive words inside one file (runs never cross files), n in {2, 3, 4}.
  * Result arrays: [0] uint64 key[U] ascending, [1] uint64 count[U], where the
- * key packs the n-gram (w0, .., w(n-1)) as w0<<32|w1 for n = 2 and
- * w0<<42|w1<<21|w2 for n = 3 (ascending keys = lexicographic order).
- * Synchronizes `stream`. Errors: INVALID_ARG (n), UNSUPPORTED (n = 3 with
- * vocab > 2^21), OVERFLOW, OOM, HIP. */
+ * key packs the n-gram (w0, .., w(n-1)) as w0<<32|w1 for n = 2,
+ * w0<<42|w1<<21|w2 for n = 3 and w0<<48|w1<<32|w2<<16|w3 for n = 4
+ * (ascending keys = lexicographic order). Synchronizes `stream`. Errors:
+ * INVALID_ARG (n), UNSUPPORTED (n = 3 with vocab > 2^21, n = 4 with vocab
+ * >= 2^16), OVERFLOW, OOM, HIP. */
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream);
 
 /* ---- tunables (read by the autotuner; per context) ---------------------- */

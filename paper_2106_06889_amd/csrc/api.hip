@@ -598,6 +598,8 @@ uint64_t gram_byte_mask(int n, int32_t V) {
   if (n == 2) {
     cover(0, b);
     cover(32, 32 + b);
+  } else if (n == 4) {
+    for (int x = 0; x < 4; ++x) cover(16 * x, 16 * x + b);
   } else {
     cover(0, b);
     cover(21, 21 + b);
@@ -837,9 +839,10 @@ int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_ve
 
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
-  if (n < 2 || n > 3) return fail(GTADOC_ERR_INVALID_ARG, "n must be 2 or 3");
+  if (n < 2 || n > 4) return fail(GTADOC_ERR_INVALID_ARG, "n must be 2, 3 or 4");
   const gt::DevGrammar& d = g->d;
   if (n == 3 && d.V > (1 << 21)) return fail(GTADOC_ERR_UNSUPPORTED, "trigram keys need vocab <= 2^21");
+  if (n == 4 && d.V > (1 << 16) - 1) return fail(GTADOC_ERR_UNSUPPORTED, "4-gram keys need vocab < 2^16");
   Call call(g->ctx, stream);
   int rc = call.begin();
   if (rc) return rc;
@@ -849,8 +852,8 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   if (!g->seq_len) {
     std::vector<Block> kept;
     auto* len = call.keep<uint64_t>(R, kept);
-    auto* head = call.keep<int32_t>(2 * R, kept);
-    auto* tail = call.keep<int32_t>(2 * R, kept);
+    auto* head = call.keep<int32_t>(3 * R, kept);  // first / last 3 words of every rule (n <= 4)
+    auto* tail = call.keep<int32_t>(3 * R, kept);
     if (!len || !head || !tail) {
       release_all(g->ctx, kept);
       return oom("head/tail buffers", 24ull * R);

@@ -1,5 +1,5 @@
 // k_seq.hip -- sequence count: occurrences of every run of n consecutive
-// words (n = 2, 3) inside one file, without decompressing.
+// words (n = 2, 3, 4) inside one file, without decompressing.
 //
 // Paper: Section "Data Structures", head and tail structures (each rule keeps
 // the first and last words of its expansion so that its parents can count
@@ -16,7 +16,9 @@
 // starts the windows whose first word is among its last n-1 words and that
 // run past its end; their remaining words come from the heads of the next
 // pieces. Per rule this gives wordSize + (n-1) x subRuleSize - (n-1)
-// windows whenever every child expands to at least n-1 words.
+// windows whenever every child expands to at least n-1 words; for n = 4 a
+// child of 2 words hands the window on to the pieces after it, and the
+// count is below that bound.
 //
 // Differences from the paper's design: head/tail buffers are filled level by
 // level from the deepest level (one launch per level) instead of a host loop
@@ -31,9 +33,12 @@ namespace gt {
 
 constexpr uint64_t kEmptyKey = ~0ull;  // never a valid packed n-gram
 
-// head[2r..2r+1] = first min(len, 2) words of exp(r), tail[2r..2r+1] = last
-// min(len, 2) words in text order; len[r] = words in exp(r). Rules of one
-// level; their children (deeper levels) are done.
+// head[kHT r ..] = first min(len, kHT) words of exp(r), tail[kHT r ..] = last
+// min(len, kHT) words in text order (unused entries -1); len[r] = words in
+// exp(r). kHT = 3 serves every n <= 4. Rules of one level; their children
+// (deeper levels) are done.
+constexpr int kHT = 3;
+
 __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
                                  int32_t* tail) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,53 +46,39 @@ __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, 
   const int32_t r = rules[i];
   const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
   uint64_t L = 0;
-  int32_t h0 = -1, h1 = -1;
+  int32_t h[kHT] = {-1, -1, -1};
   int hc = 0;
   for (int64_t q = a; q < b; ++q) {
     const int32_t s = g.sym[q];
     if (s >= 0) {
       ++L;
-      if (hc == 0) h0 = s, hc = 1;
-      else if (hc == 1) h1 = s, hc = 2;
+      if (hc < kHT) h[hc++] = s;
     } else {
-      const int32_t c = -s;
+      const int64_t c = -(int64_t)s;
       const uint64_t lc = len[c];
       L += lc;
-      const int take = lc < 2 ? (int)lc : 2;
-      for (int j = 0; j < take && hc < 2; ++j) {
-        const int32_t x = head[2 * (int64_t)c + j];
-        if (hc == 0) h0 = x, hc = 1;
-        else h1 = x, hc = 2;
-      }
+      const int take = lc < kHT ? (int)lc : kHT;
+      for (int j = 0; j < take && hc < kHT; ++j) h[hc++] = head[kHT * c + j];
     }
   }
-  int32_t t_last = -1, t_prev = -1;  // collected from the right
+  int32_t tr[kHT] = {-1, -1, -1};  // collected from the right: tr[0] is the last word
   int tc = 0;
-  for (int64_t q = b - 1; q >= a && tc < 2; --q) {
+  for (int64_t q = b - 1; q >= a && tc < kHT; --q) {
     const int32_t s = g.sym[q];
     if (s >= 0) {
-      if (tc == 0) t_last = s, tc = 1;
-      else t_prev = s, tc = 2;
+      tr[tc++] = s;
     } else {
-      const int32_t c = -s;
+      const int64_t c = -(int64_t)s;
       const uint64_t lc = len[c];
-      const int take = lc < 2 ? (int)lc : 2;
-      for (int j = take - 1; j >= 0 && tc < 2; --j) {
-        const int32_t x = tail[2 * (int64_t)c + j];
-        if (tc == 0) t_last = x, tc = 1;
-        else t_prev = x, tc = 2;
-      }
+      const int take = lc < kHT ? (int)lc : kHT;
+      for (int j = take - 1; j >= 0 && tc < kHT; --j) tr[tc++] = tail[kHT * c + j];
     }
   }
   len[r] = L;
-  head[2 * (int64_t)r] = h0;
-  head[2 * (int64_t)r + 1] = h1;
-  if (L >= 2) {
-    tail[2 * (int64_t)r] = t_prev;
-    tail[2 * (int64_t)r + 1] = t_last;
-  } else {
-    tail[2 * (int64_t)r] = t_last;
-    tail[2 * (int64_t)r + 1] = -1;
+#pragma unroll
+  for (int j = 0; j < kHT; ++j) {
+    head[kHT * (int64_t)r + j] = h[j];
+    tail[kHT * (int64_t)r + j] = j < tc ? tr[tc - 1 - j] : -1;
   }
 }
 
@@ -137,40 +128,43 @@ __device__ __forceinline__ void table_add(uint64_t* table, uint64_t mask, uint64
 
 __device__ __forceinline__ uint64_t pack_gram(const int32_t* x, int n) {
   if (n == 2) return (uint64_t)(uint32_t)x[0] << 32 | (uint32_t)x[1];
-  return (uint64_t)(uint32_t)x[0] << 42 | (uint64_t)(uint32_t)x[1] << 21 | (uint32_t)x[2];
+  if (n == 3) return (uint64_t)(uint32_t)x[0] << 42 | (uint64_t)(uint32_t)x[1] << 21 | (uint32_t)x[2];
+  return (uint64_t)(uint32_t)x[0] << 48 | (uint64_t)(uint32_t)x[1] << 32 | (uint64_t)(uint32_t)x[2] << 16 |
+         (uint32_t)x[3];
 }
 
 // Words of the piece at body position q: a word, or the first (head) / last
-// (tail) min(len, 2) words of a child's expansion.
+// (tail) min(len, m) words of a child's expansion, m = n - 1 <= kHT.
 struct Piece {
-  int32_t w[2];
+  int32_t w[kHT];
   int cnt;
 };
 
-__device__ __forceinline__ Piece piece_head(const DevGrammar& g, const uint64_t* len, const int32_t* head, int32_t s) {
+__device__ __forceinline__ Piece piece_head(const uint64_t* len, const int32_t* head, int32_t s, int m) {
   Piece p;
   if (s >= 0) {
     p.w[0] = s, p.cnt = 1;
   } else {
     const int64_t c = -(int64_t)s;
     const uint64_t lc = len[c];
-    p.cnt = lc < 2 ? (int)lc : 2;
-    p.w[0] = head[2 * c];
-    p.w[1] = head[2 * c + 1];
+    p.cnt = lc < (uint64_t)m ? (int)lc : m;
+#pragma unroll
+    for (int x = 0; x < kHT; ++x) p.w[x] = x < p.cnt ? head[kHT * c + x] : -1;
   }
   return p;
 }
 
-__device__ __forceinline__ Piece piece_tail(const DevGrammar& g, const uint64_t* len, const int32_t* tail, int32_t s) {
+__device__ __forceinline__ Piece piece_tail(const uint64_t* len, const int32_t* tail, int32_t s, int m) {
   Piece p;
   if (s >= 0) {
     p.w[0] = s, p.cnt = 1;
   } else {
     const int64_t c = -(int64_t)s;
     const uint64_t lc = len[c];
-    p.cnt = lc < 2 ? (int)lc : 2;
-    p.w[0] = tail[2 * c];
-    p.w[1] = tail[2 * c + 1];
+    const int k = lc < (uint64_t)kHT ? (int)lc : kHT;  // tail entries held
+    p.cnt = lc < (uint64_t)m ? (int)lc : m;
+#pragma unroll
+    for (int x = 0; x < kHT; ++x) p.w[x] = x < p.cnt ? tail[kHT * c + (k - p.cnt) + x] : -1;
   }
   return p;
 }
@@ -248,18 +242,18 @@ __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int 
         wt = g.w[r];
       }
       if (wt == 0) continue;
-      const Piece st = piece_tail(g, len, tail, v[k]);
+      const Piece st = piece_tail(len, tail, v[k], n - 1);
       const int starts = st.cnt < n - 1 ? st.cnt : n - 1;
       // words after the piece: heads of the next pieces, at most n-1 of them
-      int32_t ahead[2];
+      int32_t ahead[kHT];
       int na = 0;
       for (int64_t q2 = q + 1; q2 < end && na < n - 1; ++q2) {
         const int32_t kk = k + (int32_t)(q2 - q);
-        const Piece p = piece_head(g, len, head, (kk < kPerThread && q0 + kk < t.len) ? v[kk] : g.sym[q2]);
+        const Piece p = piece_head(len, head, (kk < kPerThread && q0 + kk < t.len) ? v[kk] : g.sym[q2], n - 1);
         for (int x = 0; x < p.cnt && na < n - 1; ++x) ahead[na++] = p.w[x];
       }
       for (int s0 = st.cnt - starts; s0 < st.cnt; ++s0) {
-        int32_t win[3];
+        int32_t win[kHT + 1];
         int wn = 0;
         for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
         for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];

@@ -128,6 +128,9 @@ WORKLOADS = {
                                seed=SEED_BASE + 3),
     "seq-20m": CorpusSpec("seq-20m", kind=1, tokens=20_000_000, vocab=200_000, zipf_s=1.1,
                           copy_frac=0.50, motif_chains=256, motif_levels=40, seed=SEED_BASE + 4),
+    # the same shape with a vocabulary that fits 4-gram keys (16 bits per word)
+    "seq4-20m": CorpusSpec("seq4-20m", kind=1, tokens=20_000_000, vocab=60_000, zipf_s=1.1,
+                           copy_frac=0.50, motif_chains=256, motif_levels=40, seed=SEED_BASE + 6),
 }
 
 

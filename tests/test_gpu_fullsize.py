@@ -130,3 +130,21 @@ def test_tv_4000files_full(capsys):
     assert np.array_equal(roff[:V + 1], want_off)
     assert np.array_equal(rfile[:nnz], file_of[rorder])
     assert np.array_equal(rtf[:nnz], cnt[rorder])
+
+
+@pytest.mark.timeout(300)
+def test_seq4_20m_full(ctx):
+    """4-gram counts on the 20M-token nested-repeat corpus with a vocabulary
+    that fits 16-bit key fields (V = 60,000)."""
+    import paper_2106_06889_amd as gt
+    c, g = synth.workload("seq4-20m")
+    T = len(c.tokens)
+    del c
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    res = G.sequence_count(4)
+    k, cnt = gt.to_u64(res.arrays[0]), gt.to_u64(res.arrays[1])
+    res.free()
+    G.free()
+    wk, wc = oracle.traverse_sequence_count(g, 4)
+    assert np.array_equal(k, wk) and np.array_equal(cnt, wc)
+    assert int(cnt.sum()) == T - 3

@@ -1,5 +1,6 @@
-"""GPU parity: n-gram sequence count (n = 2, 3) through the C ABI against the
-oracle (traversal and brute force), bit-exact keys and counts."""
+"""GPU parity: n-gram sequence count (n = 2, 3, and 4 where the vocabulary
+fits 16-bit key fields) through the C ABI against the oracle (traversal and
+brute force), bit-exact keys and counts."""
 import json
 import os
 
@@ -39,7 +40,9 @@ def gpu_sc(G, n):
     return k, c
 
 
-def check(ctx, g, ns=(2, 3), brute=True):
+def check(ctx, g, ns=None, brute=True):
+    if ns is None:
+        ns = (2, 3, 4) if g.vocab < (1 << 16) else (2, 3)
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
     try:
         for n in ns:
@@ -99,10 +102,16 @@ def test_argument_errors(ctx):
     import paper_2106_06889_amd as gt
     d, g = gold("e1_sequitur_abcdbc.json")
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
-    for n in (1, 4):
+    for n in (1, 5):
         with pytest.raises(gt.GtadocError) as e:
             G.sequence_count(n)
         assert e.value.code == gt.ERR_INVALID_ARG
+    G.free()
+    wide = synth.Grammar(g.rule_off, g.sym, g.file_off, 1 << 16)
+    G = ctx.load(wide.rule_off, wide.sym, wide.file_off, wide.vocab)
+    with pytest.raises(gt.GtadocError) as e:
+        G.sequence_count(4)  # 16-bit key fields, and the all-ones key marks empty slots
+    assert e.value.code == gt.ERR_UNSUPPORTED
     G.free()
     big = synth.Grammar(g.rule_off, g.sym, g.file_off, (1 << 21) + 1)
     G = ctx.load(big.rule_off, big.sym, big.file_off, big.vocab)
@@ -112,3 +121,28 @@ def test_argument_errors(ctx):
     k, c = gpu_sc(G, 2)  # bigrams still fine
     assert int(c.sum()) == 11
     G.free()
+
+
+def test_fourgrams_single_file_recipe(ctx):
+    """n = 4 on the 200K-token single-file recipe (V = 5,000): Sequitur
+    children of 2 words, shorter than n - 1, hand windows on to the next
+    pieces."""
+    c, g = synth.workload("wc-200k")
+    check(ctx, g, ns=(4,))
+    k, cn = oracle.sc_text(c.tokens, c.file_off, 4, c.vocab)
+    kk, cc = gpu_sc_of(ctx, g, 4)
+    assert np.array_equal(kk, k) and np.array_equal(cc, cn)
+
+
+def test_fourgrams_nested_recipe_scaled(ctx):
+    c, g = synth.workload("seq4-20m", scale=0.05)
+    check(ctx, g, ns=(4,), brute=False)
+    assert int(gpu_sc_of(ctx, g, 4)[1].sum()) == len(c.tokens) - 3
+
+
+def gpu_sc_of(ctx, g, n):
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        return gpu_sc(G, n)
+    finally:
+        G.free()
