@@ -852,8 +852,8 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   if (!g->seq_len) {
     std::vector<Block> kept;
     auto* len = call.keep<uint64_t>(R, kept);
-    auto* head = call.keep<int32_t>(3 * R, kept);  // first / last 3 words of every rule (n <= 4)
-    auto* tail = call.keep<int32_t>(3 * R, kept);
+    auto* head = call.keep<int32_t>(4 * R, kept);  // first / last 3 words of every rule (n <= 4), 16 B rows
+    auto* tail = call.keep<int32_t>(4 * R, kept);
     if (!len || !head || !tail) {
       release_all(g->ctx, kept);
       return oom("head/tail buffers", 24ull * R);

@@ -33,11 +33,13 @@ namespace gt {
 
 constexpr uint64_t kEmptyKey = ~0ull;  // never a valid packed n-gram
 
-// head[kHT r ..] = first min(len, kHT) words of exp(r), tail[kHT r ..] = last
-// min(len, kHT) words in text order (unused entries -1); len[r] = words in
-// exp(r). kHT = 3 serves every n <= 4. Rules of one level; their children
-// (deeper levels) are done.
+// head[4r ..] = first min(len, kHT) words of exp(r), tail[4r ..] = last
+// min(len, kHT) words in text order (unused entries -1; rows padded to 16
+// bytes so a row is one vector load); len[r] = words in exp(r). kHT = 3
+// serves every n <= 4. Rules of one level; their children (deeper levels)
+// are done.
 constexpr int kHT = 3;
+constexpr int kHTRow = 4;
 
 __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
                                  int32_t* tail) {
@@ -58,7 +60,7 @@ __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, 
       const uint64_t lc = len[c];
       L += lc;
       const int take = lc < kHT ? (int)lc : kHT;
-      for (int j = 0; j < take && hc < kHT; ++j) h[hc++] = head[kHT * c + j];
+      for (int j = 0; j < take && hc < kHT; ++j) h[hc++] = head[kHTRow * c + j];
     }
   }
   int32_t tr[kHT] = {-1, -1, -1};  // collected from the right: tr[0] is the last word
@@ -71,15 +73,18 @@ __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, 
       const int64_t c = -(int64_t)s;
       const uint64_t lc = len[c];
       const int take = lc < kHT ? (int)lc : kHT;
-      for (int j = take - 1; j >= 0 && tc < kHT; --j) tr[tc++] = tail[kHT * c + j];
+      for (int j = take - 1; j >= 0 && tc < kHT; --j) tr[tc++] = tail[kHTRow * c + j];
     }
   }
   len[r] = L;
-#pragma unroll
-  for (int j = 0; j < kHT; ++j) {
-    head[kHT * (int64_t)r + j] = h[j];
-    tail[kHT * (int64_t)r + j] = j < tc ? tr[tc - 1 - j] : -1;
-  }
+  v4i32 hv, tv;
+  hv.x = h[0], hv.y = h[1], hv.z = h[2], hv.w = -1;
+  tv.x = tc > 0 ? tr[tc - 1] : -1;
+  tv.y = tc > 1 ? tr[tc - 2] : -1;
+  tv.z = tc > 2 ? tr[tc - 3] : -1;
+  tv.w = -1;
+  *reinterpret_cast<v4i32*>(head + kHTRow * (int64_t)r) = hv;
+  *reinterpret_cast<v4i32*>(tail + kHTRow * (int64_t)r) = tv;
 }
 
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
@@ -140,16 +145,22 @@ struct Piece {
   int cnt;
 };
 
+// A buffer row is loaded (one 16-byte load) without waiting for len[c],
+// then the piece's words are picked in registers.
+__device__ __forceinline__ int32_t pick3(const int32_t (&raw)[kHT], int i) {
+  return i == 0 ? raw[0] : (i == 1 ? raw[1] : raw[2]);
+}
+
 __device__ __forceinline__ Piece piece_head(const uint64_t* len, const int32_t* head, int32_t s, int m) {
   Piece p;
   if (s >= 0) {
     p.w[0] = s, p.cnt = 1;
   } else {
     const int64_t c = -(int64_t)s;
+    const v4i32 row = *reinterpret_cast<const v4i32*>(head + kHTRow * c);
+    p.w[0] = row.x, p.w[1] = row.y, p.w[2] = row.z;
     const uint64_t lc = len[c];
     p.cnt = lc < (uint64_t)m ? (int)lc : m;
-#pragma unroll
-    for (int x = 0; x < kHT; ++x) p.w[x] = x < p.cnt ? head[kHT * c + x] : -1;
   }
   return p;
 }
@@ -160,11 +171,13 @@ __device__ __forceinline__ Piece piece_tail(const uint64_t* len, const int32_t* 
     p.w[0] = s, p.cnt = 1;
   } else {
     const int64_t c = -(int64_t)s;
+    const v4i32 row = *reinterpret_cast<const v4i32*>(tail + kHTRow * c);
+    const int32_t raw[kHT] = {row.x, row.y, row.z};
     const uint64_t lc = len[c];
     const int k = lc < (uint64_t)kHT ? (int)lc : kHT;  // tail entries held
     p.cnt = lc < (uint64_t)m ? (int)lc : m;
 #pragma unroll
-    for (int x = 0; x < kHT; ++x) p.w[x] = x < p.cnt ? tail[kHT * c + (k - p.cnt) + x] : -1;
+    for (int x = 0; x < kHT; ++x) p.w[x] = pick3(raw, k - p.cnt + x);  // used for x < cnt only
   }
   return p;
 }
@@ -203,9 +216,10 @@ __device__ __forceinline__ void seq_add(SeqLds& L, uint64_t* table, uint64_t mas
 
 // Owned windows, position-parallel over the tiles of all bodies. The root is
 // split at file boundaries: windows never cross files.
-__global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int n, const uint64_t* len,
-                                                              const int32_t* head, const int32_t* tail,
-                                                              uint64_t* table, uint64_t mask, uint32_t* overflow) {
+template <int n>
+__global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, const uint64_t* len, const int32_t* head,
+                                                              const int32_t* tail, uint64_t* table, uint64_t mask,
+                                                              uint32_t* overflow) {
   __shared__ SeqLds L;
   for (int x = threadIdx.x; x < kSeqSlots; x += blockDim.x) L.key[x] = kEmptyKey, L.val[x] = 0;
   const Tile t = tile_begin(g, blockIdx.x, L.roff);  // (synchronizes)
@@ -245,7 +259,7 @@ __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int 
       const Piece st = piece_tail(len, tail, v[k], n - 1);
       const int starts = st.cnt < n - 1 ? st.cnt : n - 1;
       // words after the piece: heads of the next pieces, at most n-1 of them
-      int32_t ahead[kHT];
+      int32_t ahead[n - 1];
       int na = 0;
       for (int64_t q2 = q + 1; q2 < end && na < n - 1; ++q2) {
         const int32_t kk = k + (int32_t)(q2 - q);
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(kTileThreads) void k_seq_windows(DevGrammar g, int 
         for (int x = 0; x < p.cnt && na < n - 1; ++x) ahead[na++] = p.w[x];
       }
       for (int s0 = st.cnt - starts; s0 < st.cnt; ++s0) {
-        int32_t win[kHT + 1];
+        int32_t win[n];
         int wn = 0;
         for (int x = s0; x < st.cnt && wn < n; ++x) win[wn++] = st.w[x];
         for (int x = 0; x < na && wn < n; ++x) win[wn++] = ahead[x];
@@ -279,7 +293,10 @@ hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, c
   k_fill_table<<<(unsigned)(fb < 8192 ? fb : 8192), 256, 0, s>>>(table, (int64_t)cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ntiles == 0) return e;
-  k_seq_windows<<<(unsigned)g.ntiles, kTileThreads, 0, s>>>(g, n, len, head, tail, table, cap - 1, overflow);
+  const unsigned grid = (unsigned)g.ntiles;
+  if (n == 2) k_seq_windows<2><<<grid, kTileThreads, 0, s>>>(g, len, head, tail, table, cap - 1, overflow);
+  else if (n == 3) k_seq_windows<3><<<grid, kTileThreads, 0, s>>>(g, len, head, tail, table, cap - 1, overflow);
+  else k_seq_windows<4><<<grid, kTileThreads, 0, s>>>(g, len, head, tail, table, cap - 1, overflow);
   return hipGetLastError();
 }
 
