@@ -22,7 +22,10 @@ constexpr int kPerThread = kTileSyms / kTileThreads;
 constexpr int kTileRuleSlots = kTileSyms + 4;
 // Passes that keep per-block tables (histograms, bucket cursors) walk
 // kSubTiles consecutive tiles per workgroup: blocks of kBlockSyms symbols.
-constexpr int kSubTiles = 4;
+// Three tiles keep the word-count scatter's LDS (rule offsets + the block's
+// staged entries) under half of a CU's 160 KB, so two 1024-thread
+// workgroups share a CU.
+constexpr int kSubTiles = 3;
 constexpr int kBlockSyms = kTileSyms * kSubTiles;
 // Word count by buckets of consecutive word ids: a bucket's counters
 // (kWcBucket x uint64) fit in LDS. Entries pack (weight << kWcBits | local id).
