@@ -63,6 +63,7 @@ constexpr uint64_t kWcMaxWeight = 1ull << (32 - kWcBits);
 struct WcScatterLds {
   int32_t roff[kTileRuleSlots];
   uint32_t stage[kBlockSyms];
+  uint16_t chunk_bucket[kBlockSyms / 64];  // bucket of entry 64k of the staged run
 };
 
 // Dynamic LDS after WcScatterLds: cur[nb], lstart[nb], gstart[nb] (uint32).
@@ -150,15 +151,19 @@ __device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t bl
     }
     __syncthreads();  // roff is rewritten by the next tile
   }
-  // copy out: the run of bucket b goes to gstart[b] .. ; lanes take consecutive entries
+  // copy out: the run of bucket b goes to gstart[b] .. ; lanes take consecutive entries.
+  // The bucket of entry e is found from the bucket of its 64-entry chunk's
+  // first entry, stepping over the few bucket starts inside the chunk
+  // (empty buckets share the next start).
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const uint32_t s0 = lstart[b], s1 = b + 1 < nb ? lstart[b + 1] : n_block;
+    for (uint32_t k = (s0 + 63) >> 6; (k << 6) < s1; ++k) L.chunk_bucket[k] = (uint16_t)b;
+  }
+  __syncthreads();
   for (uint32_t e = threadIdx.x; e < n_block; e += blockDim.x) {
-    int lo = 0, hi = nb - 1;  // last bucket with lstart <= e (empty buckets share the next start)
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (lstart[mid] <= e) lo = mid;
-      else hi = mid - 1;
-    }
-    entries[gstart[lo] + (e - lstart[lo])] = L.stage[e];
+    int b = L.chunk_bucket[e >> 6];
+    while (b + 1 < nb && lstart[b + 1] <= e) ++b;
+    entries[gstart[b] + (e - lstart[b])] = L.stage[e];
   }
   __syncthreads();  // LDS is reused by the next block of a persistent grid
 }
