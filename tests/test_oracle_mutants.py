@@ -145,3 +145,43 @@ def test_mutant_is_caught(tmp_path, mutant):
     old, new = MUTANTS[mutant]
     assert src.count(old) == 1, f"mutation site for {mutant} not unique"
     assert not run_pins(tmp_path, mutant, src.replace(old, new))
+
+
+def _ranked_variant(order_keys):
+    """A copy of the ranked inverted index with another sort key list."""
+    import oracle
+
+    def ranked(tv_off, tv_word, tv_cnt, vocab):
+        tv_off = np.asarray(tv_off, dtype=np.int64)
+        word = np.asarray(tv_word, dtype=np.int64)
+        tf = np.asarray(tv_cnt, dtype=np.uint64)
+        file = np.repeat(np.arange(len(tv_off) - 1, dtype=np.int64), np.diff(tv_off))
+        order = np.lexsort(order_keys(file, tf.astype(np.int64), word))
+        off = np.zeros(vocab + 1, np.int64)
+        np.cumsum(np.bincount(word, minlength=vocab), out=off[1:])
+        return off, file[order].astype(np.uint32), tf[order]
+    return ranked, oracle
+
+
+RANKED_MUTANTS = {
+    "tf_ascending": lambda f, t, w: (f, t, w),
+    "ties_by_file_descending": lambda f, t, w: (-f, -t, w),
+    "tf_before_word": lambda f, t, w: (f, w, -t),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(RANKED_MUTANTS))
+def test_ranked_mutant_is_caught(mutant):
+    """The hand-worked ranked inverted index fixture catches a wrong order."""
+    with open(os.path.join(GOLD, "e4_ranked_inverted_index.json")) as fh:
+        d = json.load(fh)
+    tokens = np.concatenate([np.asarray(x, np.int32) for x in d["files"]])
+    file_off = np.concatenate([[0], np.cumsum([len(x) for x in d["files"]])]).astype(np.int64)
+    g = synth.compress(tokens, file_off, d["vocab"])
+    ranked, oracle = _ranked_variant(RANKED_MUTANTS[mutant])
+    off, word, cnt = oracle.traverse_term_vector(g)
+    want = d["ranked_inverted_index"]
+    good = oracle.ranked_inverted_index(off, word, cnt, d["vocab"])
+    assert good[1].tolist() == want["file"] and good[2].tolist() == want["tf"]
+    bad = ranked(off, word, cnt, d["vocab"])
+    assert bad[1].tolist() != want["file"] or bad[2].tolist() != want["tf"]
