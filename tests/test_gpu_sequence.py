@@ -63,7 +63,7 @@ def check(ctx, g, ns=None, brute=True):
 def test_golden(ctx, name):
     d, g = gold(name)
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
-    for n, key in ((2, "bigrams"), (3, "trigrams")):
+    for n, key in ((2, "bigrams"), (3, "trigrams"), (4, "fourgrams")):
         if key in d:
             k, c = gpu_sc(G, n)
             assert {int(a): int(b) for a, b in zip(k, c)} == {int(a): b for a, b in d[key].items()}

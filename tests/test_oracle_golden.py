@@ -57,7 +57,7 @@ def test_weights_wc_sort(name):
 @pytest.mark.parametrize("name", ["e1_sequitur_abcdbc.json", "e2_two_files.json", "e3_head_tail.json"])
 def test_sequences(name):
     d, g = load(name)
-    for n, key in ((2, "bigrams"), (3, "trigrams")):
+    for n, key in ((2, "bigrams"), (3, "trigrams"), (4, "fourgrams")):
         if key not in d:
             continue
         want = {int(k): v for k, v in d[key].items()}
