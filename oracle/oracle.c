@@ -42,16 +42,20 @@ void or_free(void* p) { free(p); }
 /* Structure of a grammar                                                   */
 /* ------------------------------------------------------------------------ */
 
-/* Structural validity: offsets monotone and in range, word ids < V, rule
- * references in [1, R), file spans tile the root body. Returns OR_OK or
- * OR_ERR_RANGE. (Background, "TADOC": rules, words and splitters are all
- * numbers; a rule is a node of the DAG and R0 is its root.) */
+/* Structural validity: offsets monotone and in range, every rule other than
+ * the root has a non-empty body, word ids < V, rule references in [1, R),
+ * file spans tile the root body. Returns OR_OK or OR_ERR_RANGE.
+ * (Background, "TADOC": rules, words and splitters are all numbers; a rule
+ * is a node of the DAG that stands for a non-empty run of symbols, and R0 is
+ * its root.) */
 int or_check_structure(const int64_t* rule_off, int64_t R, const int32_t* sym, int64_t S,
                        const int64_t* file_off, int64_t F, int32_t V) {
   if (R < 1 || F < 1 || V <= 0) return OR_ERR_ARG;
   if (rule_off[0] != 0 || rule_off[R] != S) return OR_ERR_RANGE;
   for (int64_t r = 0; r < R; ++r)
     if (rule_off[r + 1] < rule_off[r]) return OR_ERR_RANGE;
+  for (int64_t r = 1; r < R; ++r)
+    if (rule_off[r + 1] == rule_off[r]) return OR_ERR_RANGE; /* empty non-root body */
   for (int64_t i = 0; i < S; ++i) {
     int64_t s = sym[i];
     if (s >= 0 && s >= V) return OR_ERR_RANGE;

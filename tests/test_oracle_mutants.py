@@ -34,6 +34,50 @@ MUTANTS = {
 }
 
 
+# Planted mistakes in the two grammar checkers, caught by the hand-built
+# cases of tests/golden/checker_cases.json.
+CHECKER_MUTANTS = {
+    "overlap_exception_widened": ("d[i].rule == d[i + 1].rule && d[i + 1].pos == d[i].pos + 1 &&",
+                                  "d[i].rule == d[i + 1].rule &&"),
+    "three_occurrences_allowed": ("} else if (j - i > 2) {", "} else if (j - i > 3) {"),
+    "root_pairs_across_files": ("    int64_t nspan = r == 0 ? F : 1;\n"
+                                "    for (int64_t f = 0; f < nspan; ++f) {\n"
+                                "      int64_t lo = r == 0 ? file_off[f] : rule_off[r];\n"
+                                "      int64_t hi = r == 0 ? file_off[f + 1] : rule_off[r + 1];",
+                                "    int64_t nspan = 1;\n"
+                                "    for (int64_t f = 0; f < nspan; ++f) {\n"
+                                "      int64_t lo = r == 0 ? file_off[f] : rule_off[r];\n"
+                                "      int64_t hi = r == 0 ? file_off[F] : rule_off[r + 1];"),
+    "utility_threshold_one": ("if (refs[r] < 2) flags |= 2;", "if (refs[r] < 1) flags |= 2;"),
+    "short_body_threshold_one": ("rule_off[r + 1] - rule_off[r] < 2) flags |= 4;",
+                                 "rule_off[r + 1] - rule_off[r] < 1) flags |= 4;"),
+    "unreachable_not_flagged": ("if (n < 0 || n != R) flags |= 8;", "if (n < 0) flags |= 8;"),
+    "structure_empty_body_allowed": ("    if (rule_off[r + 1] == rule_off[r]) return OR_ERR_RANGE; /* empty non-root body */\n",
+                                     ""),
+    "structure_offsets_unchecked": ("    if (rule_off[r + 1] < rule_off[r]) return OR_ERR_RANGE;\n", ""),
+}
+
+
+def checker_pins_hold(o) -> bool:
+    """Every hand-built checker case gives its exact value."""
+    with open(os.path.join(GOLD, "checker_cases.json")) as f:
+        d = json.load(f)
+
+    def gram(c):
+        return synth.Grammar(np.array(c["rule_off"], np.int64), np.array(c["sym"], np.int32),
+                             np.array(c["file_off"], np.int64), d["vocab"])
+    try:
+        for c in d["sequitur"]:
+            if o.check_sequitur(gram(c)) != c["flags"]:
+                return False
+        for c in d["structure"]:
+            if o.check_structure(gram(c)) != c["result"]:
+                return False
+    except (RuntimeError, IndexError, ValueError):
+        return False
+    return True
+
+
 def load_variant(tmp_path, name, src_text):
     d = tmp_path / name
     d.mkdir()
@@ -107,7 +151,7 @@ def pins_hold(o) -> bool:
     return True
 
 
-def _child(so_dir, name):
+def _child(so_dir, name, which):
     import faulthandler
     faulthandler.disable()
     mod = importlib.util.module_from_spec(
@@ -115,15 +159,16 @@ def _child(so_dir, name):
     mod.__spec__.loader.exec_module(mod)
     mod._LIB_PATH = os.path.join(so_dir, "liboracle.so")
     mod._lib = None
-    os._exit(0 if pins_hold(mod) else 1)
+    ok = checker_pins_hold(mod) if which == "checker" else pins_hold(mod)
+    os._exit(0 if ok else 1)
 
 
-def run_pins(tmp_path, name, src_text) -> bool:
+def run_pins(tmp_path, name, src_text, which="analytics") -> bool:
     """Pins of a variant, in a forked child: a variant that crashes (a planted
     out-of-bounds write, say) counts as caught."""
     load_variant(tmp_path, name, src_text)
     ctx = multiprocessing.get_context("fork")
-    p = ctx.Process(target=_child, args=(str(tmp_path / name), name))
+    p = ctx.Process(target=_child, args=(str(tmp_path / name), name, which))
     p.start()
     p.join(120)
     if p.is_alive():
@@ -135,7 +180,18 @@ def run_pins(tmp_path, name, src_text) -> bool:
 
 def test_original_passes(tmp_path):
     with open(SRC) as f:
-        assert run_pins(tmp_path, "original", f.read())
+        src = f.read()
+    assert run_pins(tmp_path, "original", src)
+    assert run_pins(tmp_path, "original_checker", src, which="checker")
+
+
+@pytest.mark.parametrize("mutant", sorted(CHECKER_MUTANTS))
+def test_checker_mutant_is_caught(tmp_path, mutant):
+    with open(SRC) as f:
+        src = f.read()
+    old, new = CHECKER_MUTANTS[mutant]
+    assert src.count(old) == 1, f"mutation site for {mutant} not unique"
+    assert not run_pins(tmp_path, mutant, src.replace(old, new), which="checker")
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS))
