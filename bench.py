@@ -54,47 +54,93 @@ def describe(name: str, query: str) -> str:
             f"Zipf({s.zipf_s}), {shape}, Sequitur grammar resident in HBM; step = {STEP[query]}")
 
 
+def host_info() -> dict:
+    """Host CPUs the baseline ran on: usable cores, model name."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0))
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def baseline_threads() -> int:
+    usable = len(os.sched_getaffinity(0))
+    try:
+        return max(1, min(usable, int(os.environ.get("OMP_NUM_THREADS", usable))))
+    except ValueError:
+        return usable
+
+
+def timed(fn, budget_s: float, max_reps: int = 20) -> tuple[float, int]:
+    """Seconds per run of fn (repeated within the budget) and the runs made."""
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or reps >= max_reps:
+            return el / reps, reps
+
+
 def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
-    """The oracle's sequential DAG traversal on the host (one core), repeated
-    within a time budget on the full grammar (word count, sequence count) or
-    run over the leading files until the budget is spent (term vector: the
-    oracle traverses file by file)."""
-    import numpy as np
+    """The oracle timed on the host: the sequential DAG traversal on one core
+    (the primary figure: the paper compares against sequential TADOC), the
+    same traversal on all usable cores, and (word count) the brute force
+    that decompresses then counts, on one core. Word count and sequence
+    count run on the whole grammar, repeated within a time budget; the term
+    vector over the leading files until the budget is spent."""
     import oracle
     import synth
     T = int(file_tokens.sum())
-    t0 = time.perf_counter()
+    threads = baseline_threads()
+    variants = []
     if query in ("tv", "rii"):
         F = g.num_files
-        f, chunk = 0, max(1, F // 400)
-        while f < F and time.perf_counter() - t0 < budget_s:
-            hi = min(F, f + chunk)
-            off, word, cnt = oracle.traverse_term_vector(synth.Grammar(g.rule_off, g.sym, g.file_off[f:hi + 1],
-                                                                       g.vocab))
-            if query == "rii":
-                oracle.ranked_inverted_index(off, word, cnt, g.vocab)
-            f = hi
-        el = time.perf_counter() - t0
-        toks = int(file_tokens[:f].sum())
+
+        def run_files(fn, budget, files_per_call):
+            f, t0 = 0, time.perf_counter()
+            while f < F and time.perf_counter() - t0 < budget:
+                hi = min(F, f + files_per_call)
+                off, word, cnt = fn(synth.Grammar(g.rule_off, g.sym, g.file_off[f:hi + 1], g.vocab))
+                if query == "rii":
+                    oracle.ranked_inverted_index(off, word, cnt, g.vocab)
+                f = hi
+            el = time.perf_counter() - t0
+            return int(file_tokens[:f].sum()) / el, f, el
         what = "term vector" + (" + ranked inverted index of each chunk" if query == "rii" else "")
-        return {"value": toks / el, "unit": "words/s", "cores": 1, "kind": "oracle",
-                "sample": f"per-file top-down traversal {what}, first {f} of {F} files "
-                          f"({toks} tokens) in {el:.1f} s"}
-    reps = 0
-    while True:
-        if query == "wc":
-            oracle.traverse_word_count(g)
-        else:
-            for n in SEQ_NS[query]:
-                oracle.traverse_sequence_count(g, n)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 20:
-            break
-    per = el / reps
-    what = "word count" if query == "wc" else "sequence count " + " and ".join(f"n={n}" for n in SEQ_NS[query])
+        chunk = max(1, F // 400)
+        v1, f1, e1 = run_files(oracle.traverse_term_vector, budget_s, chunk)
+        vp, fp, ep = run_files(lambda h: oracle.traverse_term_vector_parallel(h, threads), budget_s / 2,
+                               chunk * threads)
+        variants.append({"value": vp, "unit": "words/s", "cores": threads,
+                         "sample": f"file-parallel top-down traversal {what} on {threads} threads, "
+                                   f"first {fp} of {F} files in {ep:.1f} s"})
+        return {"value": v1, "unit": "words/s", "cores": 1, "kind": "oracle",
+                "sample": f"per-file top-down traversal {what}, first {f1} of {F} files in {e1:.1f} s",
+                "variants": variants, "host": host_info()}
+    if query == "wc":
+        per, reps = timed(lambda: oracle.traverse_word_count(g), budget_s)
+        what = "word count"
+        pp, rp = timed(lambda: oracle.traverse_word_count_parallel(g, threads), budget_s / 3)
+        variants.append({"value": T / pp, "unit": "words/s", "cores": threads,
+                         "sample": f"whole grammar, {rp} run(s) of the traversal word count with the "
+                                   f"accumulation on {threads} threads, {pp:.3f} s each"})
+        pb, rb = timed(lambda: oracle.brute_word_count(g), budget_s / 3, max_reps=5)
+        variants.append({"value": T / pb, "unit": "words/s", "cores": 1,
+                         "sample": f"whole grammar, {rb} run(s) of decompress-then-count, {pb:.3f} s each"})
+    else:
+        per, reps = timed(lambda: [oracle.traverse_sequence_count(g, n) for n in SEQ_NS[query]], budget_s)
+        what = "sequence count " + " and ".join(f"n={n}" for n in SEQ_NS[query])
     return {"value": T / per, "unit": "words/s", "cores": 1, "kind": "oracle",
-            "sample": f"whole grammar, {reps} run(s) of the sequential traversal {what}, {per:.3f} s each"}
+            "sample": f"whole grammar, {reps} run(s) of the sequential traversal {what}, {per:.3f} s each",
+            "variants": variants, "host": host_info()}
 
 
 PHASE_KERNEL = {"levels": "k_levels"}
@@ -126,6 +172,13 @@ def measured_traffic(phase: str, workload: str):
             if h.hexdigest() == rec["sources_sha256"]:
                 return int(rec["traffic_bytes_per_launch"])
     return None
+
+
+def dist(ms: list) -> dict:
+    """Median and 90th percentile of per-step device times (ms)."""
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "n": int(a.size)}
 
 
 def roofline(name: str, nbytes: float, us: float) -> dict:
@@ -223,23 +276,81 @@ def run_query(args):
     assert st["tokens"] == T, (st["tokens"], T)
     log(f"stats: {st}")
 
+    def read_phases():
+        out = {}
+        for ph in gt.PHASES:
+            ms, n = ctx.phase_time(ph, reset=True)
+            if n:
+                out[ph] = {"avg_us": 1e3 * ms / n, "count": n}
+        return out
+
+    # timed region: K whole steps back to back (the `value`), kernel timers on,
+    # a HIP event pair around every step for the per-step device times
     ctx.set_param(gt.PARAM_TIMING, 1)
-    for ph in gt.PHASES:
-        ctx.phase_time(ph, reset=True)
+    read_phases()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
+        ev[k][0].record(stream)
         step()
+        ev[k][1].record(stream)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    ctx.set_param(gt.PARAM_TIMING, 0)
     ms_step = 1e3 * t_total / args.steps
-    phases = {}
-    for ph in gt.PHASES:
-        ms, n = ctx.phase_time(ph)
-        if n:
-            phases[ph] = {"avg_us": 1e3 * ms / n, "count": n}
+    phases = read_phases()
+    warm_ms = [a.elapsed_time(b) for a, b in ev]
     log(f"{args.steps} steps in {t_total:.3f}s ({ms_step:.3f} ms/step); phases {phases}")
+
+    # cold steps: a 1 GiB write before each evicts the 256 MB Infinity Cache
+    # and the L2s, so the step reads the grammar from HBM (not timed in `value`)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    n_cold = max(5, min(args.steps, 10))
+
+    def cold_times(fn):
+        times = []
+        for k in range(n_cold):
+            flush.fill_(k & 0xff)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        return times
+
+    read_phases()
+    cold_ms = cold_times(step)
+    phases_cold = read_phases()
+    # the query alone on a grammar loaded once (weights cached at load)
+    query_only = None
+    if q == "wc":
+        Gq = ctx.load(ro, sym, fo, V, borrow=True)
+
+        def query():
+            gt.gtadoc._check(lib.gtadoc_word_count(Gq.handle, counts.data_ptr(), sp))
+            gt.gtadoc._check(lib.gtadoc_sort(Gq.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
+                                             num.data_ptr(), sp))
+        for _ in range(2):
+            query()
+        evq = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for k in range(args.steps):
+            evq[k][0].record(stream)
+            query()
+            evq[k][1].record(stream)
+        torch.cuda.synchronize()
+        qwarm = [a.elapsed_time(b) for a, b in evq]
+        qcold = cold_times(query)
+        Gq.free()
+        query_only = {"what": "word count + sort on a grammar loaded once (weights cached at load)",
+                      "warm_ms": dist(qwarm), "cold_ms": dist(qcold),
+                      "words_per_s_warm_median": T / (dist(qwarm)["median"] * 1e-3)}
+    ctx.set_param(gt.PARAM_TIMING, 0)
+    # release the library's device objects before the interpreter shuts down
+    ctx.close()
+    del counts, ids, scnt, num, ro, sym, fo, flush
+    torch.cuda.synchronize()
 
     # algorithmic bytes of each timed kernel (what the method must move):
     #   level walk  : non-root bodies, rule offsets, weights written, level order written
@@ -255,10 +366,12 @@ def run_query(args):
         U = sum(sizes.get(f"U{n}", 0) for n in ns)
         cands["seq_windows"] = ("owned windows into the exact table (k_seq_windows)",
                                 (len(ns) * (4 * S + 8 * (R + 1) + 16 * R) + 8 * R + 16 * R + 16 * U) / len(ns))
-    if q in ("tv", "rii") and "tv_tables" in phases and "tv_reduce" in phases:
+    if q in ("tv", "rii"):
         # the term vector pass (bottom-up tables + per-file reduce), per call
-        phases["term_vector"] = {"avg_us": phases["tv_tables"]["avg_us"] + phases["tv_reduce"]["avg_us"],
-                                 "count": phases["tv_tables"]["count"]}
+        for ph in (phases, phases_cold):
+            if "tv_tables" in ph and "tv_reduce" in ph:
+                ph["term_vector"] = {"avg_us": ph["tv_tables"]["avg_us"] + ph["tv_reduce"]["avg_us"],
+                                     "count": ph["tv_tables"]["count"]}
         cands["term_vector"] = ("term vector pass (rule tables + per-file reduce)",
                                 4 * S + 8 * (R + 1) + 8 * (F + 1) + 12 * sizes.get("nnz_tv", 0))
     dom = max((p for p in cands if p in phases), key=lambda p: phases[p]["avg_us"] * phases[p]["count"])
@@ -266,6 +379,12 @@ def run_query(args):
     if args.scale == 1.0:
         roof["traffic"] = measured_traffic(dom, args.workload)
     others = {p: roofline(cands[p][0], cands[p][1], phases[p]["avg_us"]) for p in cands if p in phases and p != dom}
+    # the same kernels in the cold steps (grammar read from HBM, not the Infinity Cache)
+    roof_cold = {p: roofline(cands[p][0], cands[p][1], phases_cold[p]["avg_us"]) for p in cands if p in phases_cold}
+    if q == "wc" and "word_count" in phases_cold:
+        # the flat pass on rule-body bytes alone (4 S + 8 (R + 1))
+        roof_cold["word_count_body_bytes"] = roofline("word count pass, rule-body bytes",
+                                                      4 * S + 8 * (R + 1), phases_cold["word_count"]["avg_us"])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -291,6 +410,11 @@ def run_query(args):
         "roofline": roof,
         "phases_us": {p: v["avg_us"] for p, v in phases.items()},
         "roofline_other": others,
+        "step_device_ms": {"warm": dist(warm_ms), "cold": dist(cold_ms),
+                           "cold_protocol": "1 GiB device write before each step"},
+        "phases_cold_us": {p: v["avg_us"] for p, v in phases_cold.items()},
+        "roofline_cold": roof_cold,
+        "query_only": query_only,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -346,6 +470,10 @@ def run_serve(args):
         log(f"lambda={frac:.2f}C ({rate:.0f} q/s): served p50 {a['p50_ms']:.2f} p99 {a['p99_ms']:.2f} ms; "
             f"plain p50 {b['p50_ms']:.2f} p99 {b['p99_ms']:.2f} ms")
     srv.close()
+    for G in loaded:
+        G.free()
+    ctx.close()
+    torch.cuda.synchronize()
     mean_T = totT / len(pairs)
     out = {
         "metric": "served queries/s at saturation (closed loop, mixed word count / term vector / bigram)",

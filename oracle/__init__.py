@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (plain C99, host only)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -67,6 +67,7 @@ def _load():
             "or_sc_text": (_i64, [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _vp]),
             "or_weights": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
             "or_wc_traverse": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp]),
+            "or_wc_traverse_par": (ctypes.c_int, [_vp, _i64, _vp, _i32, _vp, ctypes.c_int]),
             "or_tv_traverse": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, _i32, _vp, _vp, _vp]),
             "or_head_tail": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.c_int, _vp, _vp]),
             "or_owned_counts": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int, _vp]),
@@ -248,6 +249,37 @@ def traverse_word_count(g) -> np.ndarray:
     wc = np.empty(g.vocab, dtype=np.uint64)
     _check(_load().or_wc_traverse(_p(ro), R, _p(sym), int(g.vocab), _p(wc)), "wc_traverse")
     return wc
+
+
+def traverse_word_count_parallel(g, threads: int) -> np.ndarray:
+    """traverse_word_count with the accumulation on `threads` host threads
+    (rule ranges, private count arrays); the same result."""
+    ro, sym, _, R, _ = _grammar(g)
+    wc = np.empty(g.vocab, dtype=np.uint64)
+    _check(_load().or_wc_traverse_par(_p(ro), R, _p(sym), int(g.vocab), _p(wc), int(threads)), "wc_traverse_par")
+    return wc
+
+
+def traverse_term_vector_parallel(g, threads: int):
+    """The per-file traversal term vector with files spread over `threads`
+    host threads (the library call releases the interpreter lock), joined in
+    file order: the same result as traverse_term_vector."""
+    from concurrent.futures import ThreadPoolExecutor
+    F = len(g.file_off) - 1
+    cuts = np.linspace(0, F, min(F, 4 * threads) + 1).astype(np.int64)
+
+    def part(k):
+        sub = type(g)(g.rule_off, g.sym, g.file_off[cuts[k]:cuts[k + 1] + 1], g.vocab)
+        return traverse_term_vector(sub)
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(part, range(len(cuts) - 1)))
+    offs, words, cnts, base = [np.zeros(1, np.int64)], [], [], 0
+    for off, word, cnt in parts:
+        offs.append(off[1:] + base)
+        base += int(off[-1])
+        words.append(word)
+        cnts.append(cnt)
+    return np.concatenate(offs), np.concatenate(words), np.concatenate(cnts)
 
 
 def traverse_term_vector(g):

@@ -399,6 +399,52 @@ int or_wc_traverse(const int64_t* rule_off, int64_t R, const int32_t* sym, int32
   return rc;
 }
 
+/* The same word count with the accumulation spread over host threads, for
+ * the CPU baseline on all cores (TADOC's coarse-grained CPU parallelism):
+ * weights as in or_weights (one sequential topological pass), then the
+ * rules are cut into `nthreads` ranges of about equal symbol count, each
+ * thread sums weight(r) * (words in body(r)) into a private count array, and
+ * the private arrays are added together. Same result as or_wc_traverse. */
+int or_wc_traverse_par(const int64_t* rule_off, int64_t R, const int32_t* sym, int32_t V, uint64_t* wc,
+                       int nthreads) {
+  if (nthreads < 1) return OR_ERR_ARG;
+  uint64_t* w = malloc(sizeof(uint64_t) * (size_t)R);
+  uint64_t* priv = calloc((size_t)nthreads * (size_t)V, sizeof(uint64_t));
+  int64_t* cut = malloc(sizeof(int64_t) * (size_t)(nthreads + 1));
+  if (!w || !priv || !cut) {
+    free(w), free(priv), free(cut);
+    return OR_ERR_NOMEM;
+  }
+  int rc = or_weights(rule_off, R, sym, w);
+  if (rc == OR_OK) {
+    /* rule ranges [cut[t], cut[t+1]) of about S / nthreads symbols each */
+    int64_t S = rule_off[R], r = 0;
+    cut[0] = 0;
+    for (int t = 1; t < nthreads; ++t) {
+      int64_t target = S / nthreads * t;
+      while (r < R && rule_off[r] < target) ++r;
+      cut[t] = r;
+    }
+    cut[nthreads] = R;
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1)
+    for (int t = 0; t < nthreads; ++t) {
+      uint64_t* mine = priv + (size_t)t * (size_t)V;
+      for (int64_t q = cut[t]; q < cut[t + 1]; ++q)
+        for (int64_t i = rule_off[q]; i < rule_off[q + 1]; ++i)
+          if (sym[i] >= 0) mine[sym[i]] += w[q];
+    }
+    memset(wc, 0, sizeof(uint64_t) * (size_t)V);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t x = 0; x < V; ++x) {
+      uint64_t sum = 0;
+      for (int t = 0; t < nthreads; ++t) sum += priv[(size_t)t * (size_t)V + (size_t)x];
+      wc[x] = sum;
+    }
+  }
+  free(w), free(priv), free(cut);
+  return rc;
+}
+
 /* Term vector by traversal: for each file, a top-down pass over the part of
  * the DAG reachable from the file's span of the root, with per-file weights
  * (the file's span counts once; each occurrence of c in body(r) adds

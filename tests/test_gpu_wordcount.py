@@ -228,3 +228,42 @@ def test_deep_chain(ctx):
             res.free()
     finally:
         G.free()
+
+
+def heavy_grammar():
+    """One file: a few random words, a run of 3 * 2^21 copies of one word,
+    a few more random words. Sequitur folds the run into doubling rules, so
+    the innermost rule (the word twice) is used 3 * 2^20 times: its words
+    take the heavy-weight path of the word-count scatter (a rule weight of
+    2^20 or more does not fit the packed entry)."""
+    rng = np.random.default_rng(77)
+    run = np.full(3 << 21, 5, np.int32)
+    tokens = np.concatenate([rng.integers(0, 40, 300, dtype=np.int32), run,
+                             rng.integers(0, 40, 200, dtype=np.int32)])
+    g = synth.compress(tokens, np.array([0, len(tokens)], np.int64), 40)
+    return tokens, g
+
+
+@pytest.mark.timeout(300)
+def test_heavy_rule_weight(ctx):
+    import torch
+    import paper_2106_06889_amd as gt
+    tokens, g = heavy_grammar()
+    w = oracle.weights(g)
+    assert int(w.max()) >= 1 << 20  # the case this test is for
+    want = oracle.wc_text(tokens, g.vocab)
+    assert np.array_equal(oracle.traverse_word_count(g), want)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        assert np.array_equal(gt.to_u64(G.word_count()), want)
+        plan = ctx.batch(2, 2 * G.stats["word_syms"])
+        try:
+            outs = [torch.full((g.vocab,), -1, dtype=torch.int64, device=ctx.device) for _ in range(2)]
+            plan.word_count([G, G], outs)
+            torch.cuda.synchronize()
+            for o in outs:
+                assert np.array_equal(gt.to_u64(o), want)
+        finally:
+            plan.close()
+    finally:
+        G.free()

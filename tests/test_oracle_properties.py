@@ -121,3 +121,19 @@ def test_workload_small_scale_end_to_end():
     c, g = synth.workload("wc-200k", scale=0.25)
     assert oracle.check_sequitur(g) == 0
     assert np.array_equal(oracle.traverse_word_count(g), oracle.wc_text(c.tokens, c.vocab))
+
+
+def test_parallel_variants_equal_sequential():
+    """The CPU-baseline variants on several host threads give the sequential
+    oracle's results exactly (rule-range word count; file-parallel term
+    vector), and both equal the brute force on the text."""
+    for seed in range(3):
+        c = synth.random_corpus(40 + seed, 1 + 3 * seed, 3000, 50)
+        g = synth.compress(c.tokens, c.file_off, 50)
+        want = oracle.wc_text(c.tokens, 50)
+        for t in (1, 3, 8):
+            assert np.array_equal(oracle.traverse_word_count_parallel(g, t), want)
+        boff, bword, bcnt = oracle.tv_text(c.tokens, c.file_off, 50)
+        for t in (1, 4):
+            off, word, cnt = oracle.traverse_term_vector_parallel(g, t)
+            assert np.array_equal(off, boff) and np.array_equal(word, bword) and np.array_equal(cnt, bcnt)
