@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 import weakref
 from dataclasses import dataclass
 
@@ -130,6 +131,10 @@ class Context:
             self.handle = None
 
     def __del__(self):
+        # no HIP call during interpreter shutdown: the runtime (and a
+        # profiler's tool library) may already be torn down
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -214,6 +219,8 @@ class Grammar:
         self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -299,6 +306,10 @@ class Batch:
     free = close
 
     def __del__(self):
+        # no HIP call during interpreter shutdown: the runtime (and a
+        # profiler's tool library) may already be torn down
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -109,6 +109,10 @@ class Server:
             res = G.sequence_count(2)
             rec.result = tuple(gt.to_u64(a) for a in res.arrays) if self.keep else None
             res.free()
+        # the call returns with its last kernels still queued (the emit after
+        # the size read-back, the key sort): the result is ready only once
+        # the stream has passed them
+        self.stream.synchronize()
 
     # --------------------------------------------------- continuous batching
     def run(self, queries: list[Query], realtime: bool = True) -> list[Record]:
