@@ -131,6 +131,21 @@ int gtadoc_free_grammar(gtadoc_grammar g);
  * Errors: INVALID_ARG, OOM, HIP. */
 int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream);
 
+/* Word count without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation. Same result and arguments as gtadoc_word_count, but the
+ * call's scratch (one 4-byte entry per word symbol of the bodies) is a
+ * static device array of the library, 128 MiB per device, held from the
+ * first context on that device until the process ends; no arena scratch is
+ * taken and no hipMalloc, hipFree or allocating library routine is called.
+ * Limit: grammars with at most 33,554,432 word symbols (stats.word_syms);
+ * larger ones fail with UNSUPPORTED before any work is queued. Every call on
+ * one device shares that array: calls that overlap on the same device (on
+ * different streams, contexts or host threads without ordering between them)
+ * race and give wrong counts; calls ordered on one stream or one context do
+ * not. Asynchronous. Errors: INVALID_ARG, UNSUPPORTED, HIP. */
+int gtadoc_word_count_noalloc(gtadoc_grammar g, uint64_t* counts, void* stream);
+
 /* Sort (an application of Section "Implementation"): the words with a
  * nonzero count, ordered by count descending, then word id ascending.
  * `word_counts` is a device array of vocab uint64 from gtadoc_word_count on

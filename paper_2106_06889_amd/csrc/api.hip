@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -91,6 +92,35 @@ class Arena {
   uint64_t cap_ = 0, in_use_ = 0, peak_ = 0;
   std::map<uint64_t, uint64_t> free_;
 };
+
+// Scratch of the allocation-free word count (gtadoc_word_count_noalloc): the
+// packed word entries of the bucketed reduction, at most kStaticEntries of
+// them (128 MiB). Each device the library runs on holds its own copy for the
+// life of the process. In host code `scratch` names a host-side stand-in, not
+// device memory: kernels receive the device address found once per device by
+// hipGetSymbolAddress (static_scratch_at).
+constexpr int64_t kStaticEntries = 32ll << 20;
+static __device__ __align__(256) uint32_t scratch[kStaticEntries];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint32_t* g_static_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up on the first call for that device. Returns hipSuccess or the
+// lookup's error.
+hipError_t static_scratch_at(int device, uint32_t** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[device]) {
+    uint32_t* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_static_ptr[device] = p;
+  }
+  *out = g_static_ptr[device];
+  return hipSuccess;
+}
 
 constexpr size_t kPinnedBytes = 64 * 1024;
 constexpr size_t kPinnedLevelAt = 1024;  // byte offset of the level offsets read back at load
@@ -297,6 +327,14 @@ int gtadoc_ctx_create(void* arena, uint64_t arena_bytes, gtadoc_ctx* out) {
     if (c->done) (void)hipEventDestroy(c->done);
     delete c;
     return fail(GTADOC_ERR_HIP, "context setup failed");
+  }
+  uint32_t* sp = nullptr;
+  const hipError_t se = static_scratch_at(c->device, &sp);
+  if (se != hipSuccess) {
+    (void)hipEventDestroy(c->done);
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return fail(GTADOC_ERR_HIP, "device address of the static scratch: %s", hipGetErrorString(se));
   }
   *out = c;
   return GTADOC_OK;
@@ -552,6 +590,32 @@ int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream) {
   int rc = call.begin();
   if (rc) return rc;
   return word_count_into(g, call, counts);
+}
+
+int gtadoc_word_count_noalloc(gtadoc_grammar g, uint64_t* counts, void* stream) {
+  if (!g || !counts) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  const gt::DevGrammar& d = g->d;
+  const int64_t W = g->st.word_syms;
+  if (d.wc_nb > 0 && W > kStaticEntries)
+    return fail(GTADOC_ERR_UNSUPPORTED,
+                "allocation-free word count holds at most %lld word symbols in its static scratch; this grammar has %lld",
+                (long long)kStaticEntries, (long long)W);
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  if (W == 0) {
+    HIP_TRY(gt::launch_fill_u64(counts, d.V, 0, s));
+    return GTADOC_OK;
+  }
+  if (d.wc_nb == 0) {  // direct atomics: no scratch at all
+    HIP_TRY(gt::launch_word_count(d, counts, s));
+    return GTADOC_OK;
+  }
+  uint32_t* entries = nullptr;
+  HIP_TRY(static_scratch_at(g->ctx->device, &entries));
+  HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, g->ctx->wc_chunk, s));
+  return GTADOC_OK;
 }
 
 int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, uint64_t* counts, int64_t* num,

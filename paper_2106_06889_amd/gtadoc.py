@@ -54,6 +54,7 @@ EXPORTS = {
     "gtadoc_grammar_stats": [_vp, _vp],
     "gtadoc_free_grammar": [_vp],
     "gtadoc_word_count": [_vp, _vp, _vp],
+    "gtadoc_word_count_noalloc": [_vp, _vp, _vp],
     "gtadoc_sort": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gtadoc_term_vector": [_vp, _vp, _vp],
     "gtadoc_inverted_index": [_vp, _vp, _vp],
@@ -232,6 +233,13 @@ class Grammar:
             out = torch.empty(self.vocab, dtype=torch.int64, device=self.ctx.device)
         assert out.dtype == torch.int64 and out.numel() == self.vocab and out.is_contiguous()
         _check(lib().gtadoc_word_count(self.handle, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def word_count_noalloc(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """Word count into the caller's int64 tensor of vocab entries, with the
+        library's static device scratch instead of arena memory."""
+        assert out.dtype == torch.int64 and out.numel() == self.vocab and out.is_contiguous()
+        _check(lib().gtadoc_word_count_noalloc(self.handle, out.data_ptr(), _stream_ptr(stream)))
         return out
 
     def sort(self, word_counts: torch.Tensor | None = None, stream=None):
