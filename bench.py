@@ -420,6 +420,142 @@ def run_query(args):
     print(json.dumps(out), flush=True)
 
 
+# ------------------------------------------- traversal / baseline comparisons
+def device_times(stream, fn, reps: int, cold: bool = False, flush=None) -> dict:
+    """Median and p90 of the device time of fn (HIP events on `stream`),
+    after two untimed runs; cold: a 1 GiB write before each run."""
+    import torch
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    ms = []
+    for k in range(reps):
+        if cold:
+            flush.fill_(k & 0xff)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return dist(ms)
+
+
+def run_compare(args):
+    """--query uncompressed: the compressed path beside analytics on the
+    uncompressed text on the same GPU (the text resident in HBM, and
+    decompression on the GPU followed by the same analytics), per query kind
+    (Evaluation, Discussion: comparison with GPU-accelerated uncompressed
+    analytics). --query tvsel: term vector by the bottom-up and the top-down
+    traversal and the selector's choice (Evaluation, Optimization Analysis:
+    top-down vs. bottom-up traversals)."""
+    import numpy as np
+    import synth
+    t0 = time.time()
+    c, g = synth.workload(args.workload, args.scale)
+    T = len(c.tokens)
+    file_tokens = np.diff(c.file_off)
+    log(f"corpus {args.workload} x{args.scale}: T={T} F={g.num_files} -> grammar R={g.num_rules} S={len(g.sym)} "
+        f"({time.time() - t0:.1f}s)")
+    import torch
+    import paper_2106_06889_amd as gt
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ro = torch.from_numpy(g.rule_off).to(dev)
+    sym = torch.from_numpy(g.sym).to(dev)
+    fo = torch.from_numpy(g.file_off).to(dev)
+    text = torch.from_numpy(c.tokens).to(dev)
+    text_off = torch.from_numpy(c.file_off).to(dev)
+    text_ro = torch.tensor([0, T], dtype=torch.int64, device=dev)
+    del c
+    V, R, S, F = g.vocab, g.num_rules, len(g.sym), g.num_files
+    ctx = gt.Context(96 * R + 72 * S + 80 * V + 64 * T + 8 * F * V + (4 << 30), dev)
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    reps = args.steps
+    counts = torch.empty(V, dtype=torch.int64, device=dev)
+    ids = torch.empty(V, dtype=torch.int32, device=dev)
+    scnt = torch.empty(V, dtype=torch.int64, device=dev)
+    num = torch.empty(1, dtype=torch.int64, device=dev)
+    lib = gt.lib()
+    sp = stream.cuda_stream
+
+    def query(G, kind):
+        if kind == "wc":
+            gt.gtadoc._check(lib.gtadoc_word_count(G.handle, counts.data_ptr(), sp))
+            gt.gtadoc._check(lib.gtadoc_sort(G.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
+                                             num.data_ptr(), sp))
+        elif kind == "tv":
+            G.term_vector().free()
+        else:
+            G.sequence_count(2).free()
+
+    out = {"metric": None, "unit": "words/s", "n_gpus": 1, "steps": reps, "warmup": 2, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": describe(args.workload, "wc") if args.scale == 1.0 else
+                      f"{args.workload} x{args.scale}", "tokens": T, "rules": R, "symbols": S, "files": F,
+                      "vocab": V}}
+    if args.query == "uncompressed":
+        kinds = ["tv"] if F > 1 else ["wc", "sc2"]
+        rows = {}
+        for kind in kinds:
+            # compressed: load (levels, weights) + query from the resident grammar
+            def comp():
+                G = ctx.load(ro, sym, fo, V, borrow=True)
+                query(G, kind)
+                G.free()
+
+            # uncompressed, resident text: the same query kernels on a one-rule grammar of the tokens
+            def plain():
+                P = ctx.load(text_ro, text, text_off, V, borrow=True)
+                query(P, kind)
+                P.free()
+
+            # decompression on the GPU, then the analytics on the text
+            Gd = ctx.load(ro, sym, fo, V, borrow=True)
+
+            def dec_plain():
+                tok, off = Gd.decompress()
+                P = ctx.load(text_ro, tok, off, V, borrow=True)
+                query(P, kind)
+                P.free()
+            r = {"compressed_ms": device_times(stream, comp, reps),
+                 "uncompressed_resident_ms": device_times(stream, plain, reps),
+                 "decompress_then_query_ms": device_times(stream, dec_plain, reps),
+                 "compressed_cold_ms": device_times(stream, comp, max(3, reps // 2), True, flush),
+                 "uncompressed_resident_cold_ms": device_times(stream, plain, max(3, reps // 2), True, flush)}
+            Gd.free()
+            r["speedup_vs_resident_text"] = r["uncompressed_resident_ms"]["median"] / r["compressed_ms"]["median"]
+            r["speedup_vs_decompress"] = r["decompress_then_query_ms"]["median"] / r["compressed_ms"]["median"]
+            rows[kind] = r
+            log(f"{kind}: compressed {r['compressed_ms']['median']:.3f} ms, text {r['uncompressed_resident_ms']['median']:.3f}"
+                f" ms, decompress+text {r['decompress_then_query_ms']['median']:.3f} ms")
+        first = rows[kinds[0]]
+        out.update({"metric": f"uncompressed words/s analysed ({'+'.join(kinds)}), compressed path vs GPU "
+                              f"uncompressed baseline",
+                    "value": T / (first["compressed_ms"]["median"] * 1e-3),
+                    "ms_per_step": first["compressed_ms"]["median"], "comparison": rows,
+                    "step": "compressed: load + query; uncompressed: load of the one-rule text grammar + the same "
+                            "query; decompress: GPU decompression + that"})
+    else:
+        Gs = ctx.load(ro, sym, fo, V, borrow=True)
+        choice = {gt.TV_TOP_DOWN: "top-down", gt.TV_BOTTOM_UP: "bottom-up"}[Gs.tv_strategy()]
+        rows = {}
+        for name, strat in (("bottom-up", gt.TV_BOTTOM_UP), ("top-down", gt.TV_TOP_DOWN)):
+            rows[name] = device_times(stream, lambda: Gs.term_vector(strat).free(), reps)
+            log(f"term vector {name}: {rows[name]['median']:.3f} ms")
+        Gs.free()
+        best = min(rows, key=lambda k: rows[k]["median"])
+        out.update({"metric": "uncompressed words/s analysed (term vector), bottom-up vs top-down traversal",
+                    "value": T / (rows[choice]["median"] * 1e-3), "ms_per_step": rows[choice]["median"],
+                    "traversals_ms": rows, "selector_choice": choice, "fastest": best,
+                    "step": "term vector on a grammar loaded once"})
+    ctx.close()
+    del text, text_off, ro, sym, fo, flush
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------------ serving
 def run_serve(args):
     import numpy as np
@@ -494,7 +630,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--query", choices=("wc", "sc", "sc4", "tv", "rii", "serve"), default="wc")
+    ap.add_argument("--query", choices=("wc", "sc", "sc4", "tv", "rii", "serve", "uncompressed", "tvsel"),
+                    default="wc")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")
@@ -521,6 +658,10 @@ def main():
         return
     if args.query == "serve":
         run_serve(args)
+        return
+    if args.query in ("uncompressed", "tvsel"):
+        args.workload = args.workload or {"uncompressed": "wc-100m", "tvsel": "tv-4files"}[args.query]
+        run_compare(args)
         return
     args.workload = args.workload or DEFAULT_WORKLOAD[args.query]
     run_query(args)

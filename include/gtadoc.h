@@ -119,6 +119,11 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t num_rul
 
 int gtadoc_grammar_stats(gtadoc_grammar g, gtadoc_stats* out);
 
+/* E: the number of distinct (parent, child) rule pairs of the DAG (root
+ * included), counted on the first call and kept. Synchronizes `stream` on
+ * the first call. Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_grammar_edges(gtadoc_grammar g, int64_t* edges, void* stream);
+
 /* Release a grammar's arena memory (after its queued work completes). */
 int gtadoc_free_grammar(gtadoc_grammar g);
 
@@ -146,6 +151,22 @@ int gtadoc_word_count(gtadoc_grammar g, uint64_t* counts, void* stream);
  * not. Asynchronous. Errors: INVALID_ARG, UNSUPPORTED, HIP. */
 int gtadoc_word_count_noalloc(gtadoc_grammar g, uint64_t* counts, void* stream);
 
+/* Decompression on the GPU (the baseline of Evaluation, Discussion,
+ * "Comparison with GPU-accelerated uncompressed analytics": analytics on the
+ * uncompressed text on the same GPU). Writes the text the grammar spells:
+ * tokens[0..T) (caller-owned device int32, T = stats.tokens) holds the words
+ * of file 0, then file 1, ...; file_off[0..F] (caller-owned device int64)
+ * gets each file's start in tokens, file_off[F] = T. Expansion lengths of the
+ * rules come first (children first), then the derivation tree is expanded
+ * one depth at a time. Scratch from the arena: 8 B per rule, 8 B per root
+ * symbol and 24 B per item of the widest depth (at most min(T, number of rule
+ * occurrences in the derivation tree)). Waits once for the occurrence count,
+ * then returns with the expansion queued on `stream`. The plain tokens can be
+ * loaded back as a one-rule grammar (rule_off {0, T}, sym = tokens,
+ * file_off) to run any query on the uncompressed text. Errors: INVALID_ARG,
+ * OOM, HIP. */
+int gtadoc_decompress(gtadoc_grammar g, int32_t* tokens, int64_t* file_off, void* stream);
+
 /* Sort (an application of Section "Implementation"): the words with a
  * nonzero count, ordered by count descending, then word id ascending.
  * `word_counts` is a device array of vocab uint64 from gtadoc_word_count on
@@ -162,6 +183,27 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
  * file f owning [off[f], off[f+1]). Synchronizes `stream` (sizes are data
  * dependent). Errors: INVALID_ARG, OOM, HIP. */
 int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream);
+
+/* Term vector with an explicit traversal (Section "Fine-Grained Thread-Level
+ * Execution Engine": both traversals exist and a selector picks one;
+ * Evaluation, Optimization Analysis, "Top-down vs. bottom-up traversals"):
+ *  GTADOC_TV_BOTTOM_UP: per-rule word tables built children first, then one
+ *    reduce over the files' root spans (suits many small files);
+ *  GTADOC_TV_TOP_DOWN: per-file rule weights pushed from the root down, 8
+ *    files at a time, then one word-count pass per file (suits few files);
+ *    needs 8 B per (file, vocabulary id) of scratch for the dense counts;
+ *  GTADOC_TV_AUTO: the selector's choice (gtadoc_term_vector_strategy).
+ * Same result layout and errors as gtadoc_term_vector (+ INVALID_ARG for an
+ * unknown strategy). */
+#define GTADOC_TV_AUTO 0
+#define GTADOC_TV_BOTTOM_UP 1
+#define GTADOC_TV_TOP_DOWN 2
+int gtadoc_term_vector_ex(gtadoc_grammar g, int strategy, gtadoc_result* out, void* stream);
+
+/* The traversal GTADOC_TV_AUTO takes for this grammar: top-down when the
+ * grammar has at most 16 files and their dense counts (8 B per file and
+ * vocabulary id) fit in 1 GiB, else bottom-up. Errors: INVALID_ARG. */
+int gtadoc_term_vector_strategy(gtadoc_grammar g, int* strategy);
 
 /* Inverted index (an application of Section "Implementation"): for every
  * word, the ascending list of files that contain it. Result arrays:
@@ -226,7 +268,9 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value);
 #define GTADOC_PHASE_TV_TABLES 4    /* term vector: bottom-up rule tables */
 #define GTADOC_PHASE_TV_REDUCE 5    /* term vector: per-file scatter + reduce */
 #define GTADOC_PHASE_LOAD 6         /* load: all device work after validation (degrees, levels, weights) */
-#define GTADOC_NUM_PHASES 7
+#define GTADOC_PHASE_DECOMPRESS 7   /* decompression: rule lengths, root positions, depth-by-depth expansion */
+#define GTADOC_PHASE_TV_TOPDOWN 8   /* term vector, top-down: per-file weights and per-file word-count passes */
+#define GTADOC_NUM_PHASES 9
 int gtadoc_ctx_phase_time(gtadoc_ctx ctx, int phase, double* total_ms, int64_t* count, int reset);
 
 /* ---- batched queries ------------------------------------------------------
@@ -250,6 +294,52 @@ int gtadoc_batch_create(gtadoc_ctx ctx, int max_items, uint64_t max_entries, gta
 int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* const* counts, int n, void* stream);
 
 int gtadoc_batch_destroy(gtadoc_batch b);
+
+/* A query of a mixed batch (gtadoc_batch_submit). */
+#define GTADOC_QUERY_WORD_COUNT 1      /* counts: caller-owned device array of vocab uint64 */
+#define GTADOC_QUERY_TERM_VECTOR 2     /* result as gtadoc_term_vector_ex(strategy) */
+#define GTADOC_QUERY_SEQUENCE_COUNT 3  /* result as gtadoc_sequence_count(n) */
+#define GTADOC_QUERY_INVERTED_INDEX 4  /* result as gtadoc_inverted_index */
+#define GTADOC_QUERY_RANKED_INVERTED_INDEX 5
+typedef struct {
+  gtadoc_grammar grammar; /* in: a grammar of the plan's context */
+  int32_t kind;           /* in: GTADOC_QUERY_* */
+  int32_t n;              /* in: n-gram length (SEQUENCE_COUNT) */
+  uint64_t* counts;       /* in: output of WORD_COUNT */
+  gtadoc_result result;   /* out: result of the other kinds (NULL on error); free with gtadoc_result_free */
+  int32_t status;         /* out: GTADOC_OK or the query's error code */
+  int32_t strategy;       /* in: TERM_VECTOR traversal (GTADOC_TV_*; 0 = the selector) */
+} gtadoc_query;
+
+/* Run a mixed batch: word counts, term vectors, sequence counts and
+ * (ranked) inverted indexes of any grammars of the plan's context. The word
+ * counts (at most the plan's max_items, word symbols within max_entries) run
+ * as one batched persistent launch sequence on `stream`, like
+ * gtadoc_batch_word_count; each other query runs on one of the plan's own
+ * streams (four, default priority; sequence counts of one grammar share a
+ * stream), all of them ordered after the context's earlier work, so their
+ * kernels overlap on the device with each other and with the word counts.
+ * The call returns once every query is queued (variable-size results
+ * synchronize their own stream for their sizes); all of the batch's work is
+ * complete when `stream` passes the point of return. Each query's status is
+ * written to q[i].status (OOM, UNSUPPORTED, ... for that query alone).
+ * Errors of the call itself: INVALID_ARG (a malformed query: null or foreign
+ * grammar, unknown kind, bad n or strategy, missing counts; too many word
+ * counts for the plan; nothing is queued then), HIP. */
+int gtadoc_batch_submit(gtadoc_batch b, gtadoc_query* q, int nq, void* stream);
+
+/* Arena bytes a query of this kind on g takes at its peak (scratch plus its
+ * result; for WORD_COUNT the scratch alone, the counts being the caller's):
+ * the admission figure of a server that keeps grammars resident. Allocation
+ * sizes depend only on the grammar and the query, so the first call for a
+ * (kind, n, strategy) runs the query once on `stream`, measures the arena's
+ * peak above its level before the query, frees the result and keeps the
+ * figure (the call synchronizes `stream`); later calls return it at once.
+ * Sequence count's head/tail buffers, built on first use and kept with the
+ * grammar, are not part of the figure. n: SEQUENCE_COUNT only; strategy:
+ * TERM_VECTOR only (GTADOC_TV_*). Errors: INVALID_ARG, UNSUPPORTED, OOM (the
+ * arena cannot hold the query now), HIP. */
+int gtadoc_query_bytes(gtadoc_grammar g, int kind, int n, int strategy, uint64_t* bytes, void* stream);
 
 /* Array `index` of a result: device pointer (inside the arena), element
  * count and element size in bytes. The result's sizes are final when the

@@ -63,10 +63,14 @@ class Arena {
       *out = Block{off, need};
       in_use_ += need;
       peak_ = std::max(peak_, in_use_);
+      peak_mark_ = std::max(peak_mark_, in_use_);
       return true;
     }
     return false;
   }
+  // Peak bytes in use above the level at the last mark() (query footprints).
+  void mark() { mark_ = peak_mark_ = in_use_; }
+  uint64_t peak_since_mark() const { return peak_mark_ - mark_; }
   void release(const Block& b) {
     if (b.size == 0) return;
     in_use_ -= b.size;
@@ -89,7 +93,7 @@ class Arena {
   uint64_t cap() const { return cap_; }
 
  private:
-  uint64_t cap_ = 0, in_use_ = 0, peak_ = 0;
+  uint64_t cap_ = 0, in_use_ = 0, peak_ = 0, mark_ = 0, peak_mark_ = 0;
   std::map<uint64_t, uint64_t> free_;
 };
 
@@ -164,6 +168,11 @@ struct gtadoc_batch_s {
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;  // private stream the launch sequence is captured on
   int64_t graph_epoch = -1;
+  // streams of the mixed batch's variable-size queries (created on first use)
+  static constexpr int kStreams = 4;
+  hipStream_t pool[kStreams] = {};
+  hipEvent_t pool_done[kStreams] = {};
+  hipEvent_t start = nullptr;
 };
 
 struct gtadoc_grammar_s {
@@ -176,6 +185,8 @@ struct gtadoc_grammar_s {
   uint64_t* seq_len = nullptr;
   int32_t* seq_head = nullptr;
   int32_t* seq_tail = nullptr;
+  std::map<int64_t, uint64_t> footprint;  // arena bytes of a query kind (gtadoc_query_bytes)
+  int64_t edges = -1;                     // distinct (parent, child) pairs (gtadoc_grammar_edges)
 };
 
 struct gtadoc_result_s {
@@ -198,12 +209,22 @@ namespace {
 class Call {
  public:
   Call(gtadoc_ctx ctx, void* stream) : ctx_(ctx), s_(static_cast<hipStream_t>(stream)) {}
+  // A call inside a batch submit: the submit orders the stream after earlier
+  // work and joins it afterwards; the scratch goes to `defer` and is released
+  // by the submit once every query of the batch is queued (the queries run
+  // concurrently on different streams, so one's scratch must not be handed
+  // to another).
+  Call(gtadoc_ctx ctx, hipStream_t stream, std::vector<Block>* defer) : ctx_(ctx), s_(stream), defer_(defer) {}
   int begin() {
     if (hipSetDevice(ctx_->device) != hipSuccess) return fail(GTADOC_ERR_HIP, "hipSetDevice failed");
-    if (ctx_->has_done && ctx_->last != s_) HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
+    if (!defer_ && ctx_->has_done && ctx_->last != s_) HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
     return GTADOC_OK;
   }
   ~Call() {
+    if (defer_) {
+      defer_->insert(defer_->end(), scratch_.begin(), scratch_.end());
+      return;
+    }
     for (const Block& b : scratch_) ctx_->arena.release(b);
     if (hipEventRecord(ctx_->done, s_) == hipSuccess) {
       ctx_->last = s_;
@@ -231,6 +252,7 @@ class Call {
  private:
   gtadoc_ctx ctx_;
   hipStream_t s_;
+  std::vector<Block>* defer_ = nullptr;
   std::vector<Block> scratch_;
 };
 
@@ -459,7 +481,9 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   // for it every level takes the atomic mode
   gt::WideBufs wide{};
   {
-    const int64_t nbk = (R + gt::kWideBucket - 1) / gt::kWideBucket;
+    int64_t nbk = 1;
+    int32_t nbk_bits = 0;
+    while (nbk * gt::kWideBucket < R) nbk <<= 1, ++nbk_bits;
     const int64_t nonroot = S - pc->root_syms;
     if (ctx->level_wide > 0 && nbk <= gt::kWideMaxBuckets && nonroot > 0 && nonroot < (1ll << 32)) {
       wide.ew = call.scratch<uint64_t>(nonroot);
@@ -467,6 +491,8 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
       wide.cur = call.scratch<uint32_t>(nbk);
       wide.seg_lo = call.scratch<uint32_t>(nbk);
       wide.nbk = (int32_t)nbk;
+      wide.nbk_bits = nbk_bits;
+      wide.slots = (int32_t)((R + nbk - 1) / nbk);
       wide.min_rules = (int32_t)std::min<int64_t>(ctx->level_wide, INT32_MAX);
       if (!wide.ew || !wide.ec || !wide.cur || !wide.seg_lo) wide = gt::WideBufs{};
     }
@@ -615,6 +641,48 @@ int gtadoc_word_count_noalloc(gtadoc_grammar g, uint64_t* counts, void* stream) 
   uint32_t* entries = nullptr;
   HIP_TRY(static_scratch_at(g->ctx->device, &entries));
   HIP_TRY(gt::launch_word_count_buckets(d, counts, entries, W, g->ctx->wc_chunk, s));
+  return GTADOC_OK;
+}
+
+int gtadoc_decompress(gtadoc_grammar g, int32_t* tokens, int64_t* file_off, void* stream) {
+  if (!g || !file_off || (g->st.tokens > 0 && !tokens)) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  const gt::DevGrammar& d = g->d;
+  const int64_t T = g->st.tokens, R = d.R, nroot = g->st.root_syms;
+  const int32_t D = (int32_t)g->st.depth;
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  auto* len = call.scratch<uint64_t>(R);
+  auto* pos = call.scratch<uint64_t>(nroot);
+  auto* sums = call.scratch<uint64_t>(gt::scan_scratch_entries(nroot));
+  auto* cnt = call.scratch<unsigned long long>(D + 3);
+  if (!len || !pos || !sums || !cnt) return oom("decompression lengths", 8ull * (R + 2 * nroot));
+  PhaseScope t(g->ctx, GTADOC_PHASE_DECOMPRESS, s);
+  HIP_TRY(gt::launch_fill_u64(reinterpret_cast<uint64_t*>(cnt), D + 3, 0, s));
+  HIP_TRY(gt::launch_rule_lengths(d, g->level_off.data(), D, len, s));
+  // rule occurrences in the derivation tree (sum of the non-root weights)
+  // bound the items of one depth, as do the tokens (items of one depth
+  // expand to disjoint, non-empty output ranges)
+  HIP_TRY(gt::launch_sum_u64(d.w + 1, R - 1, cnt + D + 2, s));
+  auto* pc = reinterpret_cast<unsigned long long*>(g->ctx->pinned);
+  HIP_TRY(hipMemcpyAsync(pc, cnt + D + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t occ = (int64_t)*pc;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(T, occ));
+  int32_t* rule_a = call.scratch<int32_t>(cap);
+  int32_t* rule_b = call.scratch<int32_t>(cap);
+  int64_t* off_a = call.scratch<int64_t>(cap);
+  int64_t* off_b = call.scratch<int64_t>(cap);
+  if (!rule_a || !rule_b || !off_a || !off_b) return oom("decompression items", 24ull * cap);
+  HIP_TRY(gt::launch_root_positions(d, len, pos, nroot, (uint64_t)T, file_off, sums, s));
+  HIP_TRY(gt::launch_expand_root(d, pos, nroot, tokens, rule_a, off_a, cnt, s));
+  for (int32_t k = 1; k <= D; ++k) {
+    HIP_TRY(gt::launch_expand_depth(d, len, rule_a, off_a, cnt + k - 1, cap, tokens, rule_b, off_b, cnt + k, s));
+    std::swap(rule_a, rule_b);
+    std::swap(off_a, off_b);
+  }
+  t.end();
   return GTADOC_OK;
 }
 
@@ -790,15 +858,101 @@ int term_vector_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, Tv
 
 }  // namespace
 
-int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
-  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
-  Call call(g->ctx, stream);
-  int rc = call.begin();
-  if (rc) return rc;
+namespace {
+// Term vector by the top-down traversal (few files): per group of kTdGroup
+// files, per-file rule weights from the root's references down the levels,
+// then one word-count pass per file with its weight column into a dense
+// F x V count matrix, compacted into the rows.
+int term_vector_topdown_into(gtadoc_grammar g, Call& call, std::vector<Block>* owner, TvArrays* out) {
+  const gt::DevGrammar& d = g->d;
+  hipStream_t s = call.stream();
+  const int64_t R = d.R, F = d.F, V = d.V, W = g->st.word_syms;
+  const int32_t D = (int32_t)g->st.depth;
+  if (d.wc_nb == 0)
+    return fail(GTADOC_ERR_UNSUPPORTED, "top-down term vector: vocabularies above 2^24 words are not supported");
+  const int64_t n = F * V;
+  const int64_t nb = (n + 4095) / 4096;
+  auto* dense = call.scratch<uint64_t>(n);
+  auto* wgrp = call.scratch<uint64_t>(R * gt::kTdGroup);
+  auto* wcol = call.scratch<uint64_t>(R);
+  auto* entries = call.scratch<uint32_t>(W);
+  auto* blk = call.scratch<uint32_t>(nb + gt::scan_scratch_entries(nb));
+  auto* tot = call.scratch<int64_t>(2);
+  auto* sums64 = call.scratch<uint64_t>(gt::scan_scratch_entries(F + 1));
+  if (!dense || !wgrp || !wcol || !entries || !blk || !tot || !sums64)
+    return oom("top-down term vector scratch", 8ull * n + 80ull * R + 4ull * W);
+  PhaseScope t(g->ctx, GTADOC_PHASE_TV_TOPDOWN, s);
+  for (int64_t f0 = 0; f0 < F; f0 += gt::kTdGroup) {
+    const int32_t nf = (int32_t)std::min<int64_t>(gt::kTdGroup, F - f0);
+    HIP_TRY(gt::launch_fill_u64(wgrp, R * gt::kTdGroup, 0, s));
+    HIP_TRY(gt::launch_td_root(d, f0, nf, wgrp, s));
+    HIP_TRY(gt::launch_td_levels(d, g->level_off.data(), D, wgrp, s));
+    for (int32_t j = 0; j < nf; ++j) {
+      HIP_TRY(gt::launch_td_column(wgrp, R, j, wcol, s));
+      gt::DevGrammar df = d;
+      df.w = wcol;
+      df.span_file = f0 + j;
+      if (W > 0) {
+        HIP_TRY(gt::launch_word_count_buckets(df, dense + (f0 + j) * V, entries, W, g->ctx->wc_chunk, s));
+      } else {
+        HIP_TRY(gt::launch_fill_u64(dense + (f0 + j) * V, V, 0, s));
+      }
+    }
+  }
+  HIP_TRY(gt::launch_td_compact_count(dense, n, blk, s));
+  HIP_TRY(gt::launch_scan_u32_ext(blk, nb, tot, blk + nb, s));
+  auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
+  HIP_TRY(hipMemcpyAsync(pc, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t NNZ = pc[0];
+  int64_t* off;
+  uint32_t* word;
+  uint64_t* cnt;
+  if (owner) {
+    off = call.keep<int64_t>(F + 1, *owner);
+    word = call.keep<uint32_t>(NNZ, *owner);
+    cnt = call.keep<uint64_t>(NNZ, *owner);
+  } else {
+    off = call.scratch<int64_t>(F + 1);
+    word = call.scratch<uint32_t>(NNZ);
+    cnt = call.scratch<uint64_t>(NNZ);
+  }
+  if (!off || !word || !cnt) return oom("term vector", 12ull * NNZ);
+  HIP_TRY(gt::launch_td_compact_write(dense, n, (int32_t)V, blk, word, cnt, s));
+  HIP_TRY(gt::launch_fill_u64(reinterpret_cast<uint64_t*>(off), F + 1, 0, s));
+  HIP_TRY(gt::launch_td_row_off(dense, F, (int32_t)V, off, s));
+  HIP_TRY(gt::launch_scan_u64_ext(reinterpret_cast<uint64_t*>(off), F + 1, nullptr, sums64, s));
+  t.end();
+  out->off = off;
+  out->word = word;
+  out->cnt = cnt;
+  out->nnz = NNZ;
+  return GTADOC_OK;
+}
+
+// The traversal the selector takes: top-down for few files whose dense
+// counts are small, bottom-up otherwise.
+constexpr int64_t kTdAutoMaxFiles = 16;
+constexpr uint64_t kTdAutoMaxDense = 1ull << 30;
+int tv_auto_strategy(gtadoc_grammar g) {
+  const int64_t F = g->d.F, V = g->d.V;
+  if (g->d.wc_nb > 0 && F <= kTdAutoMaxFiles && 8ull * (uint64_t)F * (uint64_t)V <= kTdAutoMaxDense)
+    return GTADOC_TV_TOP_DOWN;
+  return GTADOC_TV_BOTTOM_UP;
+}
+
+int term_vector_any_into(gtadoc_grammar g, int strategy, Call& call, std::vector<Block>* owner, TvArrays* out) {
+  if (strategy == GTADOC_TV_AUTO) strategy = tv_auto_strategy(g);
+  if (strategy == GTADOC_TV_TOP_DOWN) return term_vector_topdown_into(g, call, owner, out);
+  return term_vector_into(g, call, owner, out);
+}
+
+int term_vector_run(gtadoc_grammar g, int strategy, Call& call, gtadoc_result* out) {
+  int rc;
   gtadoc_result res = new_result(g->ctx);
   if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
   TvArrays a;
-  rc = term_vector_into(g, call, &res->blocks, &a);
+  rc = term_vector_any_into(g, strategy, call, &res->blocks, &a);
   if (rc) {
     (void)hipStreamSynchronize(call.stream());
     release_all(g->ctx, res->blocks);
@@ -811,6 +965,31 @@ int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
   res->na = 3;
   res->tv_of = g;
   *out = res;
+  return GTADOC_OK;
+}
+
+int term_vector_entry(gtadoc_grammar g, int strategy, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (strategy != GTADOC_TV_AUTO && strategy != GTADOC_TV_BOTTOM_UP && strategy != GTADOC_TV_TOP_DOWN)
+    return fail(GTADOC_ERR_INVALID_ARG, "unknown term vector strategy %d", strategy);
+  Call call(g->ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  return term_vector_run(g, strategy, call, out);
+}
+}  // namespace
+
+int gtadoc_term_vector(gtadoc_grammar g, gtadoc_result* out, void* stream) {
+  return term_vector_entry(g, GTADOC_TV_AUTO, out, stream);
+}
+
+int gtadoc_term_vector_ex(gtadoc_grammar g, int strategy, gtadoc_result* out, void* stream) {
+  return term_vector_entry(g, strategy, out, stream);
+}
+
+int gtadoc_term_vector_strategy(gtadoc_grammar g, int* strategy) {
+  if (!g || !strategy) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  *strategy = tv_auto_strategy(g);
   return GTADOC_OK;
 }
 
@@ -857,15 +1036,19 @@ int inverted_index_from(gtadoc_grammar g, Call& call, const TvArrays& a, bool ra
   return GTADOC_OK;
 }
 
+int inverted_index_run(gtadoc_grammar g, bool ranked, Call& call, gtadoc_result* out) {
+  TvArrays a;
+  const int rc = term_vector_any_into(g, GTADOC_TV_AUTO, call, nullptr, &a);
+  if (rc) return rc;
+  return inverted_index_from(g, call, a, ranked, out);
+}
+
 int inverted_index_entry(gtadoc_grammar g, bool ranked, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   Call call(g->ctx, stream);
   int rc = call.begin();
   if (rc) return rc;
-  TvArrays a;
-  rc = term_vector_into(g, call, nullptr, &a);
-  if (rc) return rc;
-  return inverted_index_from(g, call, a, ranked, out);
+  return inverted_index_run(g, ranked, call, out);
 }
 
 int inverted_index_from_tv_entry(gtadoc_grammar g, gtadoc_result term_vector, bool ranked, gtadoc_result* out,
@@ -901,19 +1084,24 @@ int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_ve
   return inverted_index_from_tv_entry(g, term_vector, true, out, stream);
 }
 
-int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
-  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+namespace {
+int sequence_args(gtadoc_grammar g, int n) {
   if (n < 2 || n > 4) return fail(GTADOC_ERR_INVALID_ARG, "n must be 2, 3 or 4");
   const gt::DevGrammar& d = g->d;
   if (n == 3 && d.V > (1 << 21)) return fail(GTADOC_ERR_UNSUPPORTED, "trigram keys need vocab <= 2^21");
   if (n == 4 && d.V > (1 << 16) - 1) return fail(GTADOC_ERR_UNSUPPORTED, "4-gram keys need vocab < 2^16");
-  Call call(g->ctx, stream);
-  int rc = call.begin();
-  if (rc) return rc;
+  return GTADOC_OK;
+}
+
+// The head/tail/len buffers of sequence count (Section "Sequence Support",
+// initialization phase), built children first on the first use and kept
+// with the grammar.
+int ensure_headtail(gtadoc_grammar g, Call& call) {
+  if (g->seq_len) return GTADOC_OK;
+  const gt::DevGrammar& d = g->d;
   hipStream_t s = call.stream();
-  const int64_t R = d.R, S = d.S;
-  // initialization phase: head/tail/len buffers, children first (kept with the grammar)
-  if (!g->seq_len) {
+  const int64_t R = d.R;
+  {
     std::vector<Block> kept;
     auto* len = call.keep<uint64_t>(R, kept);
     auto* head = call.keep<int32_t>(4 * R, kept);  // first / last 3 words of every rule (n <= 4), 16 B rows
@@ -931,6 +1119,15 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
     g->blocks.insert(g->blocks.end(), kept.begin(), kept.end());
     g->seq_len = len, g->seq_head = head, g->seq_tail = tail;
   }
+  return GTADOC_OK;
+}
+
+int sequence_count_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* out) {
+  const gt::DevGrammar& d = g->d;
+  hipStream_t s = call.stream();
+  const int64_t S = d.S;
+  int rc = ensure_headtail(g, call);
+  if (rc) return rc;
   // graph traversal phase: owned windows into an exact table sized from the
   // per-rule bound (at most n-1 windows start at every body position): the
   // table holds at least as many slots as there can be distinct keys (the
@@ -985,6 +1182,17 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   res->na = 2;
   *out = res;
   return GTADOC_OK;
+}
+}  // namespace
+
+int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  int rc = sequence_args(g, n);
+  if (rc) return rc;
+  Call call(g->ctx, stream);
+  rc = call.begin();
+  if (rc) return rc;
+  return sequence_count_run(g, n, call, out);
 }
 
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
@@ -1078,6 +1286,11 @@ int gtadoc_batch_destroy(gtadoc_batch b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (int k = 0; k < gtadoc_batch_s::kStreams; ++k) {
+    if (b->pool[k]) (void)hipStreamSynchronize(b->pool[k]), (void)hipStreamDestroy(b->pool[k]);
+    if (b->pool_done[k]) (void)hipEventDestroy(b->pool_done[k]);
+  }
+  if (b->start) (void)hipEventDestroy(b->start);
   (void)hipEventDestroy(b->done);
   (void)hipHostFree(b->host);
   release_all(b->ctx, b->blocks);
@@ -1155,6 +1368,186 @@ int gtadoc_batch_word_count(gtadoc_batch b, const gtadoc_grammar* gs, uint64_t* 
   }
   HIP_TRY(hipEventRecord(b->done, s));
   b->launched = true;
+  return GTADOC_OK;
+}
+
+int gtadoc_batch_submit(gtadoc_batch b, gtadoc_query* q, int nq, void* stream) {
+  if (!b || nq < 0 || (nq > 0 && !q)) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  gtadoc_ctx ctx = b->ctx;
+  std::vector<gtadoc_grammar> wc_g;
+  std::vector<uint64_t*> wc_out;
+  std::vector<int> other;
+  for (int i = 0; i < nq; ++i) {
+    gtadoc_query& x = q[i];
+    if (!x.grammar || x.grammar->ctx != ctx) return fail(GTADOC_ERR_INVALID_ARG, "query %d: null or foreign grammar", i);
+    switch (x.kind) {
+      case GTADOC_QUERY_WORD_COUNT:
+        if (!x.counts) return fail(GTADOC_ERR_INVALID_ARG, "query %d: null counts", i);
+        wc_g.push_back(x.grammar);
+        wc_out.push_back(x.counts);
+        break;
+      case GTADOC_QUERY_TERM_VECTOR:
+        if (x.strategy != GTADOC_TV_AUTO && x.strategy != GTADOC_TV_BOTTOM_UP && x.strategy != GTADOC_TV_TOP_DOWN)
+          return fail(GTADOC_ERR_INVALID_ARG, "query %d: unknown term vector strategy %d", i, x.strategy);
+        other.push_back(i);
+        break;
+      case GTADOC_QUERY_SEQUENCE_COUNT:
+        if (x.n < 2 || x.n > 4) return fail(GTADOC_ERR_INVALID_ARG, "query %d: n must be 2, 3 or 4", i);
+        other.push_back(i);
+        break;
+      case GTADOC_QUERY_INVERTED_INDEX:
+      case GTADOC_QUERY_RANKED_INVERTED_INDEX:
+        other.push_back(i);
+        break;
+      default:
+        return fail(GTADOC_ERR_INVALID_ARG, "query %d: unknown kind %d", i, x.kind);
+    }
+  }
+  if ((int)wc_g.size() > b->max_items)
+    return fail(GTADOC_ERR_INVALID_ARG, "%d word counts exceed the plan (%d)", (int)wc_g.size(), b->max_items);
+  for (int i = 0; i < nq; ++i) q[i].status = GTADOC_OK, q[i].result = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the other queries start after the context's earlier work, not after this batch's word counts
+  Call outer(ctx, stream);
+  int rc = outer.begin();
+  if (rc) return rc;
+  if (!other.empty()) {
+    if (!b->start) HIP_TRY(hipEventCreateWithFlags(&b->start, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(b->start, s));
+  }
+  if (!wc_g.empty()) {
+    rc = gtadoc_batch_word_count(b, wc_g.data(), wc_out.data(), (int)wc_g.size(), stream);
+    if (rc) {
+      for (int i = 0; i < nq; ++i)
+        if (q[i].kind == GTADOC_QUERY_WORD_COUNT) q[i].status = rc;
+      if (rc == GTADOC_ERR_HIP) return rc;
+    }
+  }
+  if (other.empty()) return GTADOC_OK;
+  bool used[gtadoc_batch_s::kStreams] = {};
+  std::vector<Block> deferred;
+  int next = 0;
+  for (int i : other) {
+    gtadoc_query& x = q[i];
+    // sequence counts of one grammar share a stream: the first builds the
+    // grammar's head/tail buffers, the later ones read them
+    const int k = x.kind == GTADOC_QUERY_SEQUENCE_COUNT
+                      ? (int)((reinterpret_cast<uintptr_t>(x.grammar) >> 4) % gtadoc_batch_s::kStreams)
+                      : next++ % gtadoc_batch_s::kStreams;
+    if (!b->pool[k]) {
+      HIP_TRY(hipStreamCreateWithFlags(&b->pool[k], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&b->pool_done[k], hipEventDisableTiming));
+    }
+    if (!used[k]) {
+      HIP_TRY(hipStreamWaitEvent(b->pool[k], b->start, 0));
+      used[k] = true;
+    }
+    Call qc(ctx, b->pool[k], &deferred);
+    rc = qc.begin();
+    if (!rc) {
+      switch (x.kind) {
+        case GTADOC_QUERY_TERM_VECTOR: rc = term_vector_run(x.grammar, x.strategy, qc, &x.result); break;
+        case GTADOC_QUERY_SEQUENCE_COUNT:
+          rc = sequence_args(x.grammar, x.n);
+          if (!rc) rc = sequence_count_run(x.grammar, x.n, qc, &x.result);
+          break;
+        case GTADOC_QUERY_INVERTED_INDEX: rc = inverted_index_run(x.grammar, false, qc, &x.result); break;
+        default: rc = inverted_index_run(x.grammar, true, qc, &x.result); break;
+      }
+    }
+    if (rc) x.result = nullptr;
+    x.status = rc;
+  }
+  // join the pool into the caller's stream; the queries' scratch goes back
+  // to the arena now (later calls on the context wait for this stream)
+  for (int k = 0; k < gtadoc_batch_s::kStreams; ++k) {
+    if (!used[k]) continue;
+    HIP_TRY(hipEventRecord(b->pool_done[k], b->pool[k]));
+    HIP_TRY(hipStreamWaitEvent(s, b->pool_done[k], 0));
+  }
+  for (const Block& blk : deferred) ctx->arena.release(blk);
+  return GTADOC_OK;
+}
+
+int gtadoc_query_bytes(gtadoc_grammar g, int kind, int n, int strategy, uint64_t* bytes, void* stream) {
+  if (!g || !bytes) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (kind == GTADOC_QUERY_TERM_VECTOR || kind == GTADOC_QUERY_INVERTED_INDEX ||
+      kind == GTADOC_QUERY_RANKED_INVERTED_INDEX) {
+    if (strategy != GTADOC_TV_AUTO && strategy != GTADOC_TV_BOTTOM_UP && strategy != GTADOC_TV_TOP_DOWN)
+      return fail(GTADOC_ERR_INVALID_ARG, "unknown term vector strategy %d", strategy);
+    if (strategy == GTADOC_TV_AUTO || kind != GTADOC_QUERY_TERM_VECTOR) strategy = tv_auto_strategy(g);
+  } else {
+    strategy = 0;
+  }
+  if (kind == GTADOC_QUERY_SEQUENCE_COUNT) {
+    const int rc = sequence_args(g, n);
+    if (rc) return rc;
+  } else if (kind >= GTADOC_QUERY_WORD_COUNT && kind <= GTADOC_QUERY_RANKED_INVERTED_INDEX) {
+    n = 0;
+  } else {
+    return fail(GTADOC_ERR_INVALID_ARG, "unknown kind %d", kind);
+  }
+  const int64_t key = (int64_t)kind * 1000 + n * 10 + strategy;
+  auto it = g->footprint.find(key);
+  if (it != g->footprint.end()) {
+    *bytes = it->second;
+    return GTADOC_OK;
+  }
+  gtadoc_ctx ctx = g->ctx;
+  // sequence count's head/tail buffers belong to the grammar, not the query
+  if (kind == GTADOC_QUERY_SEQUENCE_COUNT && !g->seq_len) {
+    Call call(ctx, stream);
+    int rc = call.begin();
+    if (!rc) rc = ensure_headtail(g, call);
+    if (rc) return rc;
+  }
+  Block out_blk{};
+  if (kind == GTADOC_QUERY_WORD_COUNT && !ctx->arena.alloc(8ull * g->d.V, &out_blk)) return oom("word counts", 8ull * g->d.V);
+  gtadoc_result res = nullptr;
+  int rc;
+  {
+    Call call(ctx, stream);
+    rc = call.begin();
+    ctx->arena.mark();
+    if (!rc) {
+      switch (kind) {
+        case GTADOC_QUERY_WORD_COUNT:
+          rc = word_count_into(g, call, reinterpret_cast<uint64_t*>(ctx->base + out_blk.off));
+          break;
+        case GTADOC_QUERY_TERM_VECTOR: rc = term_vector_run(g, strategy, call, &res); break;
+        case GTADOC_QUERY_SEQUENCE_COUNT: rc = sequence_count_run(g, n, call, &res); break;
+        case GTADOC_QUERY_INVERTED_INDEX: rc = inverted_index_run(g, false, call, &res); break;
+        default: rc = inverted_index_run(g, true, call, &res); break;
+      }
+    }
+  }
+  const uint64_t peak = ctx->arena.peak_since_mark();
+  (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (res) gtadoc_result_free(res);
+  if (out_blk.size) ctx->arena.release(out_blk);
+  if (rc) return rc;
+  g->footprint[key] = peak;
+  *bytes = peak;
+  return GTADOC_OK;
+}
+
+int gtadoc_grammar_edges(gtadoc_grammar g, int64_t* edges, void* stream) {
+  if (!g || !edges) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (g->edges < 0) {
+    Call call(g->ctx, stream);
+    int rc = call.begin();
+    if (rc) return rc;
+    hipStream_t s = call.stream();
+    auto* flag = call.scratch<uint8_t>(g->d.R);
+    auto* cnt = call.scratch<unsigned long long>(1);
+    if (!flag || !cnt) return oom("edge count", (uint64_t)g->d.R);
+    HIP_TRY(gt::launch_count_edges(g->d, g->st.root_syms, flag, cnt, s));
+    auto* pc = reinterpret_cast<unsigned long long*>(g->ctx->pinned);
+    HIP_TRY(hipMemcpyAsync(pc, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->edges = (int64_t)*pc;
+  }
+  *edges = g->edges;
   return GTADOC_OK;
 }
 

@@ -74,6 +74,7 @@ struct DevGrammar {
   uint32_t* wc_off;          // [wc_nb * nslot] bucket-major exclusive offsets of word entries
   int32_t rc_nb;             // rule buckets for in-degrees (0: too many rules, direct atomics)
   uint32_t* rc_off;          // [rc_nb * nslot] bucket-major exclusive offsets of reference entries
+  int64_t span_file = -1;    // word-count pass: -1 = every root word has weight 1; f = only file f's root words
 };
 
 // Load-phase scalars written by the kernels and read back once.
@@ -94,18 +95,20 @@ struct LoadCounters {
 
 // Buffers of the bucketed mode of the level walk (wide levels): the
 // references of every non-root body, grouped by the referenced rule's bucket
-// of kWideBucket consecutive ids; bucket b owns [off[b], off[b+1]) of ew/ec,
-// filled level after level (cur[b] = end of what is written, seg_lo[b] = end
-// of what is reduced). ew == nullptr disables the mode.
-constexpr int kWideBits = 12;
-constexpr int kWideBucket = 1 << kWideBits;
+// (bucket = id mod nbk, slot = id / nbk, nbk a power of two); bucket b owns
+// [off[b], off[b+1]) of ew/ec, filled level after level (cur[b] = end of what
+// is written, seg_lo[b] = end of what is reduced). ew == nullptr disables the
+// mode.
+constexpr int kWideBucket = 4096;  // most slots per bucket (LDS table of the reduce)
 constexpr int kWideMaxBuckets = 16384;
 struct WideBufs {
   uint64_t* ew;      // weight of the referencing rule
-  uint16_t* ec;      // referenced rule id & (kWideBucket - 1)
+  uint16_t* ec;      // slot of the referenced rule in its bucket
   uint32_t* cur;     // [nbk]
   uint32_t* seg_lo;  // [nbk]
-  int32_t nbk;
+  int32_t nbk;       // power of two, nbk * kWideBucket >= R
+  int32_t nbk_bits;  // log2(nbk)
+  int32_t slots;     // ceil(R / nbk) <= kWideBucket
   int32_t min_rules;  // levels with at least this many rules use the bucketed mode
 };
 
@@ -199,6 +202,35 @@ hipError_t launch_ii(const int64_t* tv_off, int64_t F, const uint32_t* tv_word, 
                      hipStream_t s);
 hipError_t launch_scan_u64_ext(uint64_t* a, int64_t n, int64_t* total, uint64_t* sums, hipStream_t s);
 hipError_t launch_scan_u32_ext(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
+
+// term vector by the top-down traversal: kTdGroup files at a time, each rule
+// holding one uint64 weight per file of the group
+constexpr int kTdGroup = 8;
+hipError_t launch_td_root(const DevGrammar& g, int64_t f0, int32_t nf, uint64_t* w, hipStream_t s);
+hipError_t launch_td_levels(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* w,
+                            hipStream_t s);
+hipError_t launch_td_column(const uint64_t* w, int64_t R, int f, uint64_t* out, hipStream_t s);
+hipError_t launch_td_compact_count(const uint64_t* dense, int64_t n, uint32_t* blk, hipStream_t s);
+hipError_t launch_td_compact_write(const uint64_t* dense, int64_t n, int32_t V, const uint32_t* blk_off, uint32_t* word,
+                                   uint64_t* cnt, hipStream_t s);
+hipError_t launch_td_row_off(const uint64_t* dense, int64_t F, int32_t V, int64_t* off, hipStream_t s);
+
+// distinct (parent, child) rule pairs: per non-root rule its distinct
+// sub-rules, plus the distinct sub-rules of the root (flags[R] scratch)
+hipError_t launch_count_edges(const DevGrammar& g, int64_t root_syms, uint8_t* flags, unsigned long long* out,
+                              hipStream_t s);
+
+// decompression (text of the grammar on the device)
+hipError_t launch_rule_lengths(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
+                               hipStream_t s);
+hipError_t launch_sum_u64(const uint64_t* a, int64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_root_positions(const DevGrammar& g, const uint64_t* len, uint64_t* pos, int64_t nroot, uint64_t T,
+                                 int64_t* file_out, uint64_t* sums, hipStream_t s);
+hipError_t launch_expand_root(const DevGrammar& g, const uint64_t* pos, int64_t nroot, int32_t* tokens,
+                              int32_t* out_rule, int64_t* out_off, unsigned long long* out_n, hipStream_t s);
+hipError_t launch_expand_depth(const DevGrammar& g, const uint64_t* len, const int32_t* in_rule, const int64_t* in_off,
+                               const unsigned long long* in_n, int64_t cap, int32_t* tokens, int32_t* out_rule,
+                               int64_t* out_off, unsigned long long* out_n, hipStream_t s);
 
 // sequence count
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,

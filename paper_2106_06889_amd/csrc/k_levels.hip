@@ -18,14 +18,10 @@
 // bucket instead of atomics. In-degrees count occurrences (a rule used twice
 // by the same parent waits for both), which gives the same levels and
 // weights.
-#include <hip/hip_cooperative_groups.h>
-
 #include "device.h"
 #include "radix.h"
 
 namespace gt {
-
-namespace cg = cooperative_groups;
 
 // Level 1 = the rules with no pending in-edge (used only by the root, or not
 // at all), compacted in rule-id order: a count per block of kBlockSyms rules,
@@ -141,40 +137,37 @@ __device__ __forceinline__ bool agg_add(LevelLds& L, int32_t c, uint64_t w) {
   return false;
 }
 
-// Grid barrier between levels: the cooperative-groups grid barrier (device
-// scope release before, acquire after). Measured on MI355X against a
-// hand-written two-level (per-XCD, then global) counter barrier, it left the
-// working workgroups faster and the level walk ~35% shorter.
-__device__ __forceinline__ void grid_barrier() { cg::this_grid().sync(); }
-
-// Barrier among the first kMidBlocks workgroups (the others have left): a
-// counter and a generation word in device memory (zero at launch). Every
-// thread releases its own writes at device scope; thread 0 arrives, the last
-// arriver resets the counter and bumps the generation, the others poll it
-// without acquiring (an acquire per poll would invalidate the caches under
-// the working workgroups), then thread 0 acquires once. Per-level timestamps
-// showed narrow levels costing ~40 us on the full grid and ~20 us on 32-64
-// workgroups.
-constexpr int kMidBlocks = 32;
-constexpr int32_t kMidRules = 48 * 1024;  // levels narrower than this run on kMidBlocks workgroups
-
-__device__ __forceinline__ void mid_barrier(uint32_t* bar, uint32_t& gen) {
-  __threadfence();
+// Barrier among the first `nblocks` workgroups of the launch (all of them,
+// or the subset that walks the narrower levels; the others have left): a
+// counter and a generation word in device memory, zero at launch, touched by
+// one thread per workgroup. The block barrier orders the workgroup's writes
+// before thread 0's arrival; the arrival is an acquire-release RMW at agent
+// scope (it publishes the workgroup's writes, and the last arriver acquires
+// everyone's), the last arriver resets the counter and bumps the generation
+// with a release RMW, and the others poll the generation with relaxed loads
+// (an acquire per poll would invalidate the caches under the working
+// workgroups) and acquire once it has moved. Measured on MI355X with 1024
+// threads per workgroup: 11 us for 256 workgroups, 2.4 us for 32, against
+// 32 us and 5 us for the cooperative-groups grid barrier.
+__device__ __forceinline__ void group_barrier(uint32_t* bar, uint32_t nblocks, uint32_t& gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t g0 = gen;
-    const uint32_t a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a == kMidBlocks - 1) {
+    const uint32_t a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == nblocks - 1) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) __builtin_amdgcn_s_sleep(1);
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   ++gen;
   __syncthreads();
 }
+
+// Levels narrower than kMidRules run on the first kMidBlocks workgroups.
+constexpr int kMidBlocks = 32;
+constexpr int32_t kMidRules = 48 * 1024;
 
 // The workgroup's list of level d+1 goes after hi with one global atomic.
 __device__ __forceinline__ void level_list_out(DevGrammar& g, int32_t* level_cnt, LevelLds& L, int32_t d, int32_t hi) {
@@ -308,18 +301,24 @@ __device__ __forceinline__ void agg_reset(LevelLds& L) {
 
 // Bucketed mode, first half of a wide level: every reference in the bodies
 // of level_rule[lo, hi) becomes an entry (weight of the referencing rule,
-// low bits of the referenced id) in its bucket's region. The workgroup counts
-// its references per bucket in LDS, reserves each bucket's share with one
-// global atomic, then writes its entries.
+// slot of the referenced rule in its bucket) in its bucket's region. The
+// workgroup counts its references per bucket in LDS, reserves each bucket's
+// share with one global atomic, then writes its entries. Buckets interleave
+// the rule ids (bucket = id mod nbk, slot = id / nbk, nbk a power of two):
+// rules referenced most often tend to have nearby ids (Sequitur numbers rules
+// by first use), and interleaving spreads them over all buckets, so the
+// per-bucket reduce is balanced (on the 10^8-token corpus the largest bucket
+// of the widest level holds 3x the mean instead of 40x).
 struct CountOp {  // bucketed mode, first pass: references per bucket, tokens
   const DevGrammar& g;
   LevelLds& L;
   uint64_t& tokens;
+  uint32_t mask;  // nbk - 1
   uint64_t wp = 0, words = 0;
   __device__ void begin(uint64_t w) { wp = w, words = 0; }
   __device__ void sym(int32_t s) {
     if (s >= 0) ++words;
-    else if (-(int64_t)s < g.R) atomicAdd(&L.u.hist[(uint32_t)(-(int64_t)s) >> kWideBits], 1u);
+    else if (-(int64_t)s < g.R) atomicAdd(&L.u.hist[(uint32_t)(-(int64_t)s) & mask], 1u);
   }
   __device__ void end() { tokens += wp * words; }
 };
@@ -333,9 +332,9 @@ struct WriteOp {  // bucketed mode, second pass: one entry per reference
   __device__ void sym(int32_t s) {
     if (s < 0 && -(int64_t)s < g.R) {
       const uint32_t c = (uint32_t)(-(int64_t)s);
-      const uint32_t at = atomicAdd(&L.u.hist[c >> kWideBits], 1u);
+      const uint32_t at = atomicAdd(&L.u.hist[c & (uint32_t)(wb.nbk - 1)], 1u);
       wb.ew[at] = wp;
-      wb.ec[at] = (uint16_t)(c & (kWideBucket - 1));
+      wb.ec[at] = (uint16_t)(c >> wb.nbk_bits);
     }
   }
   __device__ void end() {}
@@ -345,7 +344,7 @@ __device__ __forceinline__ void wide_scatter(DevGrammar& g, const WideBufs& wb, 
                                              int64_t tid, int64_t nthreads, uint64_t& tokens) {
   for (int k = threadIdx.x; k < wb.nbk; k += blockDim.x) L.u.hist[k] = 0;
   __syncthreads();
-  CountOp count{g, L, tokens};
+  CountOp count{g, L, tokens, (uint32_t)(wb.nbk - 1)};
   walk_bodies(g, L, lo, hi, tid, nthreads, count);
   for (int k = threadIdx.x; k < wb.nbk; k += blockDim.x) {
     const uint32_t h = L.u.hist[k];
@@ -357,10 +356,10 @@ __device__ __forceinline__ void wide_scatter(DevGrammar& g, const WideBufs& wb, 
 }
 
 // Bucketed mode, second half: each bucket's new entries are summed in a
-// dense LDS table by the one workgroup that owns the bucket, which then
-// applies weight and retired in-edges to every referenced rule with plain
-// read-modify-writes (no other workgroup touches the bucket's rules) and
-// lists the rules whose last in-edge retired.
+// dense LDS table (one slot per rule of the bucket) by the one workgroup that
+// owns the bucket, which then applies weight and retired in-edges to every
+// referenced rule with plain read-modify-writes (no other workgroup touches
+// the bucket's rules) and lists the rules whose last in-edge retired.
 __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_t* level_cnt, const WideBufs& wb,
                                             LevelLds& L, int32_t d, int32_t hi) {
   for (int32_t b = blockIdx.x; b < wb.nbk; b += gridDim.x) {
@@ -368,35 +367,23 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
     __syncthreads();
     const uint32_t s0 = L.seg[0], s1 = L.seg[1];
     if (s0 != s1) {
-      // the bucket's weights and pending counts are loaded before the entries
-      // are summed, so the flush does not wait for them
-      constexpr int kPer = kWideBucket / kLevelThreads;
-      uint64_t wpre[kPer];
-      int32_t ppre[kPer];
-#pragma unroll
-      for (int x = 0; x < kPer; ++x) {
-        const int32_t c = b * kWideBucket + (int32_t)threadIdx.x + x * kLevelThreads;
-        wpre[x] = c < g.R ? g.w[c] : 0;
-        ppre[x] = c < g.R ? pend[c] : 0;
-      }
-      for (int k = threadIdx.x; k < kWideBucket; k += blockDim.x) L.u.dense.wsum[k] = 0, L.u.dense.cnt[k] = 0;
+      for (int k = threadIdx.x; k < wb.slots; k += blockDim.x) L.u.dense.wsum[k] = 0, L.u.dense.cnt[k] = 0;
       __syncthreads();
       for (uint32_t e = s0 + threadIdx.x; e < s1; e += blockDim.x) {
-        const uint32_t k = wb.ec[e] & (kWideBucket - 1);
+        const uint32_t k = wb.ec[e];
         const uint64_t wv = wb.ew[e];
         if (wv) atomicAdd(reinterpret_cast<unsigned long long*>(&L.u.dense.wsum[k]), (unsigned long long)wv);
         atomicAdd(&L.u.dense.cnt[k], 1u);
       }
       __syncthreads();
-#pragma unroll
-      for (int x = 0; x < kPer; ++x) {
-        const int k = (int)threadIdx.x + x * kLevelThreads;
-        const uint32_t n = L.u.dense.cnt[k];
-        const int32_t c = b * kWideBucket + k;
+      for (int k0 = 0; k0 < wb.slots; k0 += kLevelThreads) {  // uniform trip count: level_append is wave-collective
+        const int k = k0 + (int)threadIdx.x;
+        const uint32_t n = k < wb.slots ? L.u.dense.cnt[k] : 0u;
+        const int32_t c = (int32_t)(((uint32_t)k << wb.nbk_bits) | (uint32_t)b);
         bool ready = false;
         if (n) {
-          g.w[c] = wpre[x] + L.u.dense.wsum[k];
-          const int32_t left = ppre[x] - (int32_t)n;
+          g.w[c] += L.u.dense.wsum[k];
+          const int32_t left = pend[c] - (int32_t)n;
           pend[c] = left;
           ready = left == 0;
         }
@@ -425,19 +412,20 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   if (threadIdx.x == 0) L.list_n = 0, L.nlong = 0;
   agg_reset(L);
   bool agg_clean = true;
+  uint32_t gen = 0;  // barrier generation (the barrier words are zero at launch)
   // wide levels: the whole grid, a grid barrier between levels
   const bool shrink = gridDim.x > (unsigned)kMidBlocks;
   while (lo < hi && (hi - lo >= (shrink ? kMidRules : kTailRules) || gridDim.x == 1)) {
     if (wb.ew && hi - lo >= wb.min_rules) {
       wide_scatter(g, wb, L, lo, hi, tid, nthreads, tokens);
-      grid_barrier();
+      group_barrier(bar, gridDim.x, gen);
       wide_reduce(g, pend, level_cnt, wb, L, d, hi);
       agg_clean = false;
     } else {
       if (!agg_clean) agg_reset(L), agg_clean = true;
       level_round(g, pend, level_cnt, L, lo, hi, d, tid, nthreads, tokens);
     }
-    grid_barrier();
+    group_barrier(bar, gridDim.x, gen);
     const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tid == 0) {
       g.level_off[d] = lo;
@@ -452,10 +440,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
     if (!agg_clean) agg_reset(L), agg_clean = true;
     const int64_t mtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t mthreads = (int64_t)kMidBlocks * blockDim.x;
-    uint32_t gen = 0;
     while (lo < hi && hi - lo >= kTailRules) {
       level_round(g, pend, level_cnt, L, lo, hi, d, mtid, mthreads, tokens);
-      mid_barrier(bar, gen);
+      group_barrier(bar, kMidBlocks, gen);
       const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (mtid == 0) {
         g.level_off[d] = lo;
@@ -470,8 +457,9 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   if (blockIdx.x == 0) {
     if (!agg_clean) agg_reset(L);
     while (lo < hi) {
+      // one workgroup: the block barriers inside the round order its global
+      // writes (level list, weights, pending counts) for the next round
       level_round(g, pend, level_cnt, L, lo, hi, d, threadIdx.x, blockDim.x, tokens);
-      __threadfence();
       __syncthreads();
       const int32_t next = L.list_total;
       if (threadIdx.x == 0) {
@@ -513,17 +501,21 @@ hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounter
 }
 
 // Capacity of every bucket of the bucketed mode: the pending in-edges of its
-// rules (one workgroup per bucket).
-__global__ __launch_bounds__(256) void k_wide_caps(const int32_t* pend, int64_t R, uint32_t* cap) {
-  __shared__ uint32_t part[4];
-  const int64_t base = (int64_t)blockIdx.x * kWideBucket;
-  uint32_t sum = 0;
-  for (int k = threadIdx.x; k < kWideBucket; k += blockDim.x)
-    if (base + k < R) sum += (uint32_t)pend[base + k];
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
+// rules (bucket = id mod nbk). Each block sums a range of kCapRules rules
+// into an LDS table by bucket, then adds it to the (zeroed) capacities.
+constexpr int kCapRules = 65536;
+__global__ __launch_bounds__(1024) void k_wide_caps(const int32_t* pend, int64_t R, uint32_t* cap, int nbk) {
+  __shared__ uint32_t h[kWideMaxBuckets];
+  for (int k = threadIdx.x; k < nbk; k += blockDim.x) h[k] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) cap[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+  const int64_t base = (int64_t)blockIdx.x * kCapRules;
+  for (int k = threadIdx.x; k < kCapRules; k += blockDim.x) {
+    const int64_t c = base + k;
+    if (c < R && pend[c]) atomicAdd(&h[c & (nbk - 1)], (uint32_t)pend[c]);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nbk; k += blockDim.x)
+    if (h[k]) atomicAdd(&cap[k], h[k]);
 }
 
 // The barrier words of the shrinking phase: 2 words after the frontier scan's scratch.
@@ -537,8 +529,10 @@ hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* 
   const WideBufs& wb = wide;
   if (wb.ew) {
     // bucket regions: exclusive scan of the capacities; both cursors start there
-    k_wide_caps<<<(unsigned)wb.nbk, 256, 0, s>>>(pend, g.R, wb.cur);
-    hipError_t e0 = hipGetLastError();
+    hipError_t e0 = launch_fill_i32(reinterpret_cast<int32_t*>(wb.cur), wb.nbk, 0, s);
+    if (e0 != hipSuccess) return e0;
+    k_wide_caps<<<(unsigned)((g.R + kCapRules - 1) / kCapRules), 1024, 0, s>>>(pend, g.R, wb.cur, wb.nbk);
+    e0 = hipGetLastError();
     if (e0 == hipSuccess) e0 = launch_scan_u32(wb.cur, wb.nbk, &lc->wide_entries, scratch, s);
     if (e0 == hipSuccess)
       e0 = hipMemcpyAsync(wb.seg_lo, wb.cur, sizeof(uint32_t) * wb.nbk, hipMemcpyDeviceToDevice, s);

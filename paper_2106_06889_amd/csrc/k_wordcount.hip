@@ -67,6 +67,10 @@ struct WcScatterLds {
 };
 
 // Dynamic LDS after WcScatterLds: cur[nb], lstart[nb], gstart[nb] (uint32).
+// kSpan: only the root words inside file g.span_file's span count (weight 1),
+// the other root words get weight 0 (the top-down term vector's pass for one
+// file); without it every root word has weight 1.
+template <bool kSpan>
 __device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t blk, uint32_t* entries, uint64_t* counts,
                                                  WcScatterLds& L, uint32_t* dyn, int64_t W) {
   const int nb = g.wc_nb;
@@ -114,6 +118,8 @@ __device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t bl
     if (b < nb) lstart[b] = base, cur[b] = base;
     base += mine[x];
   }
+  int64_t span_lo = 0, span_hi = 0;
+  if (kSpan) span_lo = g.file_off[g.span_file], span_hi = g.file_off[g.span_file + 1];
   __syncthreads();
   for (int sub = 0; sub < kSubTiles; ++sub) {
     const int64_t tile = blk * kSubTiles + sub;
@@ -142,10 +148,15 @@ __device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t bl
         }
         const int32_t s = v[k];
         if (s >= 0) {
+          uint64_t we = wr;
+          if (kSpan && t.r0 + j == 0) {
+            const int64_t qa = t.a + q;
+            we = qa >= span_lo && qa < span_hi ? 1ull : 0ull;
+          }
           const uint32_t at = atomicAdd(&cur[s >> kWcBits], 1u);
-          const bool light = wr < kWcMaxWeight;
-          L.stage[at] = (light ? (uint32_t)(wr << kWcBits) : 0u) | (uint32_t)(s & (kWcBucket - 1));
-          if (!light) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[s]), (unsigned long long)wr);
+          const bool light = we < kWcMaxWeight;
+          L.stage[at] = (light ? (uint32_t)(we << kWcBits) : 0u) | (uint32_t)(s & (kWcBucket - 1));
+          if (!light) atomicAdd(reinterpret_cast<unsigned long long*>(&counts[s]), (unsigned long long)we);
         }
       }
     }
@@ -168,11 +179,12 @@ __device__ __forceinline__ void wc_scatter_block(const DevGrammar& g, int64_t bl
   __syncthreads();  // LDS is reused by the next block of a persistent grid
 }
 
+template <bool kSpan>
 __global__ __launch_bounds__(kWcScatterThreads) void k_wc_scatter(DevGrammar g, uint32_t* entries, uint64_t* counts,
                                                                   int64_t W) {
   __shared__ WcScatterLds L;
   extern __shared__ uint32_t lds_wc[];
-  wc_scatter_block(g, blockIdx.x, entries, counts, L, lds_wc, W);
+  wc_scatter_block<kSpan>(g, blockIdx.x, entries, counts, L, lds_wc, W);
 }
 
 // Reduce: the entry array is cut into chunks (bucket sizes follow the word
@@ -245,7 +257,10 @@ hipError_t launch_word_count_buckets(const DevGrammar& g, uint64_t* counts, uint
   hipError_t e = launch_fill_u64(counts, g.V, 0, s);
   if (e != hipSuccess) return e;
   if (g.ntiles == 0 || W == 0) return hipSuccess;
-  k_wc_scatter<<<(unsigned)g.nblk, kWcScatterThreads, sizeof(uint32_t) * 3 * g.wc_nb, s>>>(g, entries, counts, W);
+  if (g.span_file >= 0)
+    k_wc_scatter<true><<<(unsigned)g.nblk, kWcScatterThreads, sizeof(uint32_t) * 3 * g.wc_nb, s>>>(g, entries, counts, W);
+  else
+    k_wc_scatter<false><<<(unsigned)g.nblk, kWcScatterThreads, sizeof(uint32_t) * 3 * g.wc_nb, s>>>(g, entries, counts, W);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_wc_reduce<<<(unsigned)((W + chunk - 1) / chunk), kWcThreads, 0, s>>>(g, entries, W, counts, chunk);
@@ -288,7 +303,7 @@ __global__ __launch_bounds__(kWcScatterThreads) void k_wcb_scatter(const BatchDe
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int i = batch_item_owner(d->scatter_base, n, it);
     const BatchItem& b = d->items[i];
-    wc_scatter_block(b.g, it - d->scatter_base[i], b.entries, b.out, L, lds_wcb, b.W);
+    wc_scatter_block<false>(b.g, it - d->scatter_base[i], b.entries, b.out, L, lds_wcb, b.W);
   }
 }
 

@@ -52,11 +52,16 @@ EXPORTS = {
     "gtadoc_ctx_usage": [_vp, _vp, _vp, _vp],
     "gtadoc_load_grammar": [_vp, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _u32, _vp, _vp],
     "gtadoc_grammar_stats": [_vp, _vp],
+    "gtadoc_grammar_edges": [_vp, _vp, _vp],
+    "gtadoc_query_bytes": [_vp, _int, _int, _int, _vp, _vp],
     "gtadoc_free_grammar": [_vp],
     "gtadoc_word_count": [_vp, _vp, _vp],
     "gtadoc_word_count_noalloc": [_vp, _vp, _vp],
+    "gtadoc_decompress": [_vp, _vp, _vp, _vp],
     "gtadoc_sort": [_vp, _vp, _vp, _vp, _vp, _vp],
     "gtadoc_term_vector": [_vp, _vp, _vp],
+    "gtadoc_term_vector_ex": [_vp, _int, _vp, _vp],
+    "gtadoc_term_vector_strategy": [_vp, _vp],
     "gtadoc_inverted_index": [_vp, _vp, _vp],
     "gtadoc_inverted_index_from_tv": [_vp, _vp, _vp, _vp],
     "gtadoc_ranked_inverted_index": [_vp, _vp, _vp],
@@ -69,11 +74,23 @@ EXPORTS = {
     "gtadoc_batch_create": [_vp, _int, _u64, _vp],
     "gtadoc_batch_word_count": [_vp, _vp, _vp, _int, _vp],
     "gtadoc_batch_destroy": [_vp],
+    "gtadoc_batch_submit": [_vp, _vp, _int, _vp],
     "gtadoc_ctx_phase_time": [_vp, _int, _vp, _vp, _int],
     "gtadoc_last_error": [],
 }
 PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING, PARAM_LEVEL_WIDE = 1, 2, 3, 4, 5
-PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6}
+PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6,
+          "decompress": 7, "tv_topdown": 8}
+TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN = 0, 1, 2
+(QUERY_WORD_COUNT, QUERY_TERM_VECTOR, QUERY_SEQUENCE_COUNT, QUERY_INVERTED_INDEX,
+ QUERY_RANKED_INVERTED_INDEX) = 1, 2, 3, 4, 5
+
+
+class QueryStruct(ctypes.Structure):
+    """gtadoc_query of the C ABI."""
+    _fields_ = [("grammar", ctypes.c_void_p), ("kind", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("counts", ctypes.c_void_p), ("result", ctypes.c_void_p), ("status", ctypes.c_int32),
+                ("strategy", ctypes.c_int32)]
 
 
 def lib() -> ctypes.CDLL:
@@ -242,6 +259,15 @@ class Grammar:
         _check(lib().gtadoc_word_count_noalloc(self.handle, out.data_ptr(), _stream_ptr(stream)))
         return out
 
+    def decompress(self, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        """The text the grammar spells, on the device: (tokens int32[T],
+        file_off int64[F+1])."""
+        T, F = int(self.stats["tokens"]), int(self.stats["files"])
+        tokens = torch.empty(max(T, 1), dtype=torch.int32, device=self.ctx.device)
+        file_off = torch.empty(F + 1, dtype=torch.int64, device=self.ctx.device)
+        _check(lib().gtadoc_decompress(self.handle, tokens.data_ptr(), file_off.data_ptr(), _stream_ptr(stream)))
+        return tokens[:T], file_off
+
     def sort(self, word_counts: torch.Tensor | None = None, stream=None):
         """(ids int32[K], counts int64[K]) device tensors, count desc then id asc."""
         V = self.vocab
@@ -256,18 +282,36 @@ class Grammar:
     def _result(self, fn, *args, stream=None) -> Result:
         h = _vp()
         _check(fn(self.handle, *args, ctypes.byref(h), _stream_ptr(stream)))
-        arrays = []
-        i = 0
-        while True:
-            p, n, eb = _vp(), _i64(), _int()
-            if lib().gtadoc_result_array(h, i, ctypes.byref(p), ctypes.byref(n), ctypes.byref(eb)) != OK:
-                break
-            arrays.append(_dev_tensor(p.value or self.ctx.arena.data_ptr(), n.value, eb.value, self.ctx.arena))
-            i += 1
-        return Result(arrays, h, self.ctx)
+        return _wrap_result(self.ctx, h)
 
-    def term_vector(self, stream=None) -> Result:
-        return self._result(lib().gtadoc_term_vector, stream=stream)
+
+    def term_vector(self, strategy: int | None = None, stream=None) -> Result:
+        """Per-file (word, count) rows: arrays (off int64[F+1], word int32[NNZ],
+        count int64[NNZ]). strategy: None/TV_AUTO (the selector), TV_BOTTOM_UP
+        or TV_TOP_DOWN."""
+        if strategy is None:
+            return self._result(lib().gtadoc_term_vector, stream=stream)
+        return self._result(lib().gtadoc_term_vector_ex, int(strategy), stream=stream)
+
+    def edges(self, stream=None) -> int:
+        """E: distinct (parent, child) rule pairs (counted once, then kept)."""
+        v = _i64()
+        _check(lib().gtadoc_grammar_edges(self.handle, ctypes.byref(v), _stream_ptr(stream)))
+        return v.value
+
+    def query_bytes(self, kind: int, n: int = 0, strategy: int = TV_AUTO, stream=None) -> int:
+        """Arena bytes a query of this kind takes at its peak (measured on the
+        first request by running it once, then kept)."""
+        v = _u64()
+        _check(lib().gtadoc_query_bytes(self.handle, int(kind), int(n), int(strategy), ctypes.byref(v),
+                                        _stream_ptr(stream)))
+        return v.value
+
+    def tv_strategy(self) -> int:
+        """The traversal the selector (TV_AUTO) takes for this grammar."""
+        v = _int()
+        _check(lib().gtadoc_term_vector_strategy(self.handle, ctypes.byref(v)))
+        return v.value
 
     def inverted_index(self, stream=None) -> Result:
         return self._result(lib().gtadoc_inverted_index, stream=stream)
@@ -289,6 +333,19 @@ class Grammar:
         return self._result(lib().gtadoc_sequence_count, n, stream=stream)
 
 
+def _wrap_result(ctx: Context, h) -> Result:
+    """A Result over the arrays of result handle h (views into the arena)."""
+    arrays = []
+    i = 0
+    while True:
+        p, n, eb = _vp(), _i64(), _int()
+        if lib().gtadoc_result_array(h, i, ctypes.byref(p), ctypes.byref(n), ctypes.byref(eb)) != OK:
+            break
+        arrays.append(_dev_tensor(p.value or ctx.arena.data_ptr(), n.value, eb.value, ctx.arena))
+        i += 1
+    return Result(arrays, h, ctx)
+
+
 class Batch:
     """A batch plan: word counts of many grammars in one launch sequence."""
 
@@ -305,6 +362,33 @@ class Batch:
         os_ = (ctypes.c_void_p * max(n, 1))(*[o.data_ptr() for o in outs])
         _check(lib().gtadoc_batch_word_count(self.handle, gs, os_, n, _stream_ptr(stream)))
         return outs
+
+    def submit(self, queries: list[dict], stream=None) -> list:
+        """A mixed batch (gtadoc_batch_submit). Each query is a dict with
+        grammar, kind (QUERY_*), and n (sequence count), counts (word count:
+        int64 tensor of vocab entries) or strategy (term vector). Returns, per
+        query, the counts tensor, a Result, or a GtadocError for a query that
+        failed alone."""
+        n = len(queries)
+        arr = (QueryStruct * max(n, 1))()
+        for i, q in enumerate(queries):
+            arr[i].grammar = q["grammar"].handle.value
+            arr[i].kind = int(q["kind"])
+            arr[i].n = int(q.get("n", 0))
+            c = q.get("counts")
+            arr[i].counts = c.data_ptr() if c is not None else None
+            arr[i].strategy = int(q.get("strategy", TV_AUTO))
+        _check(lib().gtadoc_batch_submit(self.handle, arr, n, _stream_ptr(stream)))
+        out = []
+        for i, q in enumerate(queries):
+            st = arr[i].status
+            if st != OK:
+                out.append(GtadocError(st, lib().gtadoc_last_error().decode()))
+            elif q["kind"] == QUERY_WORD_COUNT:
+                out.append(q["counts"])
+            else:
+                out.append(_wrap_result(self.ctx, _vp(arr[i].result)))
+        return out
 
     def close(self):
         if self.handle and self.ctx.handle:

@@ -2,17 +2,19 @@
 
 Queries (word count, term vector, bigram count) arrive over time against any
 of the resident grammars. `Server.run` is continuous batching: every step
-admits what has arrived, launches all admitted word counts as one batch
-(one launch sequence over many grammars, see gtadoc_batch_word_count), and
-runs the admitted term-vector and bigram queries behind it; queries that
-arrive while a step is on the GPU join the next step. Admission is by
-memory: a step's word counts must fit the batch plan's entry scratch, and a
-term-vector or bigram query is admitted only while the arena has room for
-its estimated scratch. `Server.run_plain` is the baseline: first come first
-served, one query per call, waiting for each to finish.
+admits what has arrived and fits, and runs it as one mixed batch
+(gtadoc_batch_submit: the word counts as one batched launch sequence, the
+other queries on the plan's streams, overlapping on the device); two plans
+alternate so the next step is admitted while the previous one runs, and
+queries that arrive meanwhile join the next step. Admission is by memory: a
+step's word counts must fit the plan's entry scratch, and a term-vector or
+bigram query is admitted only while the arena's free bytes cover its
+footprint as the library measures it (gtadoc_query_bytes). `Server.run_plain`
+is the baseline: first come first served, one query per call, waiting for
+each to finish.
 
 Latency = arrival time to the moment the host sees the query's result on the
-device (its completion event, or the end of a synchronizing call).
+device (the step's completion event, or the end of a synchronizing call).
 """
 from __future__ import annotations
 
@@ -69,30 +71,60 @@ def percentiles(records: list[Record]) -> dict:
 
 
 class Server:
+    """Continuous batching over resident grammars.
+
+    Every step admits what has arrived and fits: word counts (at most
+    max_batch, one per grammar per step, word symbols within the plan) and
+    term-vector / bigram queries while the arena's free bytes cover their
+    footprint (gtadoc_query_bytes, measured by the library per grammar and
+    kind), at most max_other per step. The step is one mixed batch
+    (gtadoc_batch_submit): the word counts as one batched launch sequence,
+    the other queries on the plan's own streams, their kernels overlapping on
+    the device. Two plans alternate, so a step is admitted and queued while
+    the previous one is still on the GPU; queries that arrive meanwhile join
+    the next step."""
+
     def __init__(self, ctx: gt.Context, grammars: list, max_batch: int = 64, max_entries: int | None = None,
-                 keep_results: bool = False):
+                 keep_results: bool = False, max_other: int = 8, plans: int = 2):
         self.ctx = ctx
         self.grammars = grammars
         self.max_batch = max_batch
+        self.max_other = max_other
         words = [int(g.stats["word_syms"]) for g in grammars]
         self.max_entries = max_entries or max(sum(sorted(words)[-max_batch:]), 1)
-        self.plan = ctx.batch(max_batch, self.max_entries)
+        self.plans = [ctx.batch(max_batch, self.max_entries) for _ in range(max(1, plans))]
         self.keep = keep_results
         self.stream = torch.cuda.current_stream()
-        self.outs = [torch.empty(g.vocab, dtype=torch.int64, device=ctx.device) for g in grammars]
+        # word-count outputs per (plan, grammar): two steps in flight never share one
+        self.outs = [dict() for _ in self.plans]
+        self._bytes = {}
 
     def close(self):
-        self.plan.close()
+        for p in self.plans:
+            p.close()
 
     # ------------------------------------------------------------ one query
-    def _estimate_bytes(self, q: Query) -> int:
-        st = self.grammars[q.grammar].stats
-        if q.kind == "sc2":
-            cap = 1 << max(10, int(2 * st["symbols"] + 1).bit_length())
-            return 16 * cap + 64 * st["symbols"]
-        if q.kind == "tv":
-            return 40 * st["tokens"] + 64 * st["rules"] + (1 << 20)
-        return 0
+    def query_bytes(self, q: Query) -> int:
+        """Arena footprint of the query (the library's measured figure)."""
+        key = (q.grammar, q.kind)
+        if key not in self._bytes:
+            G = self.grammars[q.grammar]
+            if q.kind == "tv":
+                self._bytes[key] = G.query_bytes(gt.QUERY_TERM_VECTOR)
+            elif q.kind == "sc2":
+                self._bytes[key] = G.query_bytes(gt.QUERY_SEQUENCE_COUNT, 2)
+            else:
+                self._bytes[key] = 0
+        return self._bytes[key]
+
+    def prepare(self):
+        """Footprints of every (grammar, kind) and the grammars' head/tail
+        buffers, before any trace runs (they are measured by running each
+        query once)."""
+        for i in range(len(self.grammars)):
+            for k in ("tv", "sc2"):
+                self.query_bytes(Query(-1, k, i, 0.0))
+        torch.cuda.synchronize()
 
     def _run_single(self, q: Query, rec: Record):
         G = self.grammars[q.grammar]
@@ -114,13 +146,30 @@ class Server:
         # the stream has passed them
         self.stream.synchronize()
 
+    def _finish(self, step, now: float, recs: dict):
+        ev, qs, got = step
+        for q, r in zip(qs, got):
+            rec = recs[q.qid]
+            rec.finish = now
+            if isinstance(r, Exception):
+                rec.result = r
+                continue
+            if q.kind == "wc":
+                rec.result = gt.to_u64(r) if self.keep else None
+            else:
+                if self.keep:
+                    rec.result = (tuple(a.cpu().numpy() for a in r.arrays) if q.kind == "tv"
+                                  else tuple(gt.to_u64(a) for a in r.arrays))
+                r.free()
+
     # --------------------------------------------------- continuous batching
     def run(self, queries: list[Query], realtime: bool = True) -> list[Record]:
         pending = sorted(queries, key=lambda q: q.arrival)
         recs = {q.qid: Record(q.qid, q.kind, q.grammar, q.arrival) for q in pending}
         queue: deque[Query] = deque()
         i, n = 0, len(pending)
-        inflight = None  # (event, [queries], [outs])
+        inflight: deque = deque()  # (event, queries, results), oldest first
+        turn = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0  # noqa: E731
         while i < n or queue or inflight:
@@ -128,51 +177,60 @@ class Server:
             while i < n and (not realtime or pending[i].arrival <= now):
                 queue.append(pending[i])
                 i += 1
-            if inflight and inflight[0].query():
-                done = clock()
-                for q, out in zip(inflight[1], inflight[2]):
-                    recs[q.qid].finish = done
-                    if self.keep:
-                        recs[q.qid].result = gt.to_u64(out)
-                inflight = None
-            if inflight is None and queue:
-                # admit: word counts into the batch (entry budget), others by arena headroom
+            while inflight and inflight[0][0].query():
+                self._finish(inflight.popleft(), clock(), recs)
+            if queue and len(inflight) < len(self.plans):
+                # admit: word counts into the batch, the others by arena headroom
                 batch, entries, rest, others = [], 0, deque(), []
-                free = self.ctx.usage()[2] - self.ctx.usage()[0]
+                in_use, _, cap = self.ctx.usage()
+                free = cap - in_use
+                seen = set()
                 while queue:
                     q = queue.popleft()
                     G = self.grammars[q.grammar]
                     if q.kind == "wc":
                         w = int(G.stats["word_syms"])
-                        dup = any(b.grammar == q.grammar for b in batch)  # one output per grammar per step
-                        if len(batch) < self.max_batch and entries + w <= self.max_entries and not dup:
+                        if len(batch) < self.max_batch and entries + w <= self.max_entries and q.grammar not in seen:
                             batch.append(q)
+                            seen.add(q.grammar)
                             entries += w
                             continue
                     else:
-                        need = self._estimate_bytes(q)
-                        if need <= free and len(others) < 4:
+                        need = self.query_bytes(q)
+                        if need <= free and len(others) < self.max_other:
                             others.append(q)
                             free -= need
                             continue
                     rest.append(q)
                 queue = rest
-                if not batch and not others and queue:
-                    others.append(queue.popleft())  # too big for any step: run it alone
+                if not batch and not others:
+                    if inflight:
+                        continue  # wait for memory to come back
+                    others.append(queue.popleft())  # too big for any step with others: alone
                 start = clock()
-                if batch:
-                    outs = [self.outs[q.grammar] for q in batch]
-                    self.plan.word_count([self.grammars[q.grammar] for q in batch], outs)
-                    ev = torch.cuda.Event()
-                    ev.record(self.stream)
-                    for q in batch:
-                        recs[q.qid].start = start
-                    inflight = (ev, batch, outs)
-                for q in others:  # queued behind the batch on the same stream
-                    recs[q.qid].start = clock()
-                    self._run_single(q, recs[q.qid])
-                    recs[q.qid].finish = clock()
-            elif inflight is None and i < n:
+                step_q = batch + others
+                slot = turn % len(self.plans)
+                outs = self.outs[slot]
+                spec = []
+                for q in step_q:
+                    G = self.grammars[q.grammar]
+                    if q.kind == "wc":
+                        if q.grammar not in outs:
+                            outs[q.grammar] = torch.empty(G.vocab, dtype=torch.int64, device=self.ctx.device)
+                        spec.append({"grammar": G, "kind": gt.QUERY_WORD_COUNT, "counts": outs[q.grammar]})
+                    elif q.kind == "tv":
+                        spec.append({"grammar": G, "kind": gt.QUERY_TERM_VECTOR})
+                    else:
+                        spec.append({"grammar": G, "kind": gt.QUERY_SEQUENCE_COUNT, "n": 2})
+                    recs[q.qid].start = start
+                got = self.plans[slot].submit(spec)
+                turn += 1
+                ev = torch.cuda.Event()
+                ev.record(self.stream)
+                inflight.append((ev, step_q, got))
+            elif inflight:
+                time.sleep(2e-5)
+            elif i < n:
                 # idle until the next arrival
                 wait = pending[i].arrival - clock()
                 if wait > 2e-4:

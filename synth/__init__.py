@@ -107,7 +107,13 @@ class CorpusSpec:
     normalize: int = 0
 
     def scaled(self, factor: float, name: str | None = None) -> "CorpusSpec":
-        """Same recipe at a fraction of the size (tokens, or the number of files)."""
+        """Same recipe at a fraction of the size: the tokens (single files and
+        normalized file sets, which keep their number of files), else the
+        number of files."""
+        if self.files > 1 and self.normalize:
+            return replace(self, name=name or f"{self.name}/x{factor:g}",
+                           tokens=max(16 * self.files, int(round(self.tokens * factor))),
+                           lognorm_median=self.lognorm_median * factor)
         if self.files > 1:
             return replace(self, name=name or f"{self.name}/x{factor:g}",
                            files=max(2, int(round(self.files * factor))))
@@ -126,6 +132,12 @@ WORKLOADS = {
                                file_min=256, file_max=5_000_000, vocab=500_000, zipf_s=1.0,
                                copy_frac=0.40, span_min=8, span_max=256, cross_file=1,
                                seed=SEED_BASE + 3),
+    # few large files (the top-down term vector's case): 4 files of about
+    # 25M tokens each, the vocabulary and reuse of tv-4000files
+    "tv-4files": CorpusSpec("tv-4files", tokens=100_000_000, files=4, lognorm_median=25_000_000.0,
+                            lognorm_sigma=0.3, file_min=1, file_max=100_000_000, vocab=500_000, zipf_s=1.0,
+                            copy_frac=0.40, span_min=8, span_max=256, cross_file=1, seed=SEED_BASE + 7,
+                            normalize=1),
     "seq-20m": CorpusSpec("seq-20m", kind=1, tokens=20_000_000, vocab=200_000, zipf_s=1.1,
                           copy_frac=0.50, motif_chains=256, motif_levels=40, seed=SEED_BASE + 4),
     # the same shape with a vocabulary that fits 4-gram keys (16 bits per word)

@@ -23,9 +23,9 @@ def ctx():
     c.close()
 
 
-def gpu_tv(G):
+def gpu_tv(G, strategy=None):
     import paper_2106_06889_amd as gt
-    res = G.term_vector()
+    res = G.term_vector(strategy)
     off = res.arrays[0].cpu().numpy()
     word = res.arrays[1].cpu().numpy().view(np.uint32)
     cnt = gt.to_u64(res.arrays[2])
@@ -53,13 +53,16 @@ def same_rii(got, want):
 
 
 def check(ctx, g, brute=True):
+    import paper_2106_06889_amd as gt
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
     try:
-        off, word, cnt = gpu_tv(G)
         woff, wword, wcnt = oracle.traverse_term_vector(g)
-        assert np.array_equal(off, woff)
-        assert np.array_equal(word, wword)
-        assert np.array_equal(cnt, wcnt)
+        # both traversals, then the selector's choice
+        for strategy in (gt.TV_BOTTOM_UP, gt.TV_TOP_DOWN, None):
+            off, word, cnt = gpu_tv(G, strategy)
+            assert np.array_equal(off, woff), strategy
+            assert np.array_equal(word, wword), strategy
+            assert np.array_equal(cnt, wcnt), strategy
         if brute:
             boff, bword, bcnt = oracle.brute_term_vector(g)
             assert np.array_equal(off, boff) and np.array_equal(word, bword) and np.array_equal(cnt, bcnt)
@@ -86,10 +89,12 @@ def test_golden_e2(ctx):
         d = json.load(f)
     g = synth.Grammar(np.array(d["grammar"]["rule_off"], np.int64), np.array(d["grammar"]["sym"], np.int32),
                       np.array(d["grammar"]["file_off"], np.int64), d["vocab"])
+    import paper_2106_06889_amd as gt
     G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
-    off, word, cnt = gpu_tv(G)
-    assert off.tolist() == d["term_vector"]["off"]
-    assert word.tolist() == d["term_vector"]["word"] and cnt.tolist() == d["term_vector"]["cnt"]
+    for strategy in (gt.TV_BOTTOM_UP, gt.TV_TOP_DOWN, None):
+        off, word, cnt = gpu_tv(G, strategy)
+        assert off.tolist() == d["term_vector"]["off"]
+        assert word.tolist() == d["term_vector"]["word"] and cnt.tolist() == d["term_vector"]["cnt"]
     ioff, ifile = gpu_ii(G)
     assert ioff.tolist() == d["inverted_index"]["off"] and ifile.tolist() == d["inverted_index"]["file"]
     G.free()
@@ -204,3 +209,37 @@ def test_ranked_ties_and_heavy_counts(ctx):
     file_off = np.concatenate([[0], np.cumsum([len(x) for x in files])]).astype(np.int64)
     g = synth.compress(tokens, file_off, 6)
     check(ctx, g, brute=False)
+
+
+def test_few_large_files_recipe_scaled(ctx):
+    """The few-large-files corpus (4 files) the top-down traversal is for."""
+    import paper_2106_06889_amd as gt
+    c, g = synth.workload("tv-4files", scale=0.01)
+    assert g.num_files == 4
+    check(ctx, g, brute=False)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    assert G.tv_strategy() == gt.TV_TOP_DOWN
+    G.free()
+
+
+def test_selector_and_strategy_errors(ctx):
+    """The selector takes top-down for few files and bottom-up for many, or
+    when the dense per-file counts would be too large; unknown strategies
+    are refused."""
+    import paper_2106_06889_amd as gt
+    c = synth.random_corpus(7, 3, 500, 50)
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    assert G.tv_strategy() == gt.TV_TOP_DOWN
+    with pytest.raises(gt.GtadocError) as e:
+        G.term_vector(7)
+    assert e.value.code == gt.ERR_INVALID_ARG
+    G.free()
+    c = synth.random_corpus(8, 40, 200, 50)
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    assert G.tv_strategy() == gt.TV_BOTTOM_UP
+    G.free()
+    G = ctx.load(g.rule_off, g.sym, g.file_off[[0, 10, 40]], 1 << 24)  # 2 files x 2^24 ids x 8 B > 1 GiB
+    assert G.tv_strategy() == gt.TV_BOTTOM_UP
+    G.free()
