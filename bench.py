@@ -248,6 +248,23 @@ def run_query(args):
             tv.free()
         G.free()
 
+    # launch shape of the load and the word-count chunk: the tuner's cache for
+    # this GPU and size, else a greedy search (the paper's parameter
+    # selection) on this grammar before anything is timed
+    from paper_2106_06889_amd import autotune
+    tune_key = f"{autotune.arch()}/load/{autotune.size_bucket(T)}"
+    tuned = "defaults"
+    if not args.no_tune:
+        if autotune.apply(ctx, tune_key):
+            tuned = "cache"
+        else:
+            res = autotune.tune_load(ctx, ro, sym, fo, V, reps=3)
+            autotune.save(tune_key, res)
+            tuned = "searched on this grammar before the timed region"
+    tuned_params = {name: ctx.get_param(p) for p, name in autotune.NAMES.items()
+                    if p in autotune.LOAD_CANDIDATES}
+    log(f"load parameters ({tuned}): {tuned_params}")
+
     for i in range(args.warmup):
         step()
         log(f"warmup {i + 1}/{args.warmup} done")
@@ -406,7 +423,7 @@ def run_query(args):
         "data": "synthetic",
         "config": {"workload": describe(args.workload, q) if args.scale == 1.0 else f"{args.workload} x{args.scale}",
                    "tokens": T, "rules": R, "symbols": S, "root_symbols": root_syms, "depth": st["depth"],
-                   "files": F, "vocab": V, **sizes},
+                   "files": F, "vocab": V, **sizes, "launch_params": tuned_params, "launch_params_from": tuned},
         "roofline": roof,
         "phases_us": {p: v["avg_us"] for p, v in phases.items()},
         "roofline_other": others,
@@ -578,7 +595,21 @@ def run_serve(args):
     loaded = [ctx.load(g.rule_off, g.sym, g.file_off, g.vocab) for g, _ in pairs]
     torch.cuda.synchronize()
     log(f"loaded; arena in use {ctx.usage()[0] / 2**30:.2f} GiB of {arena / 2**30:.2f}")
+    # launch parameters of the batched word count: the tuner's cache for this
+    # GPU and size, else a greedy search on a sample of the grammars (saved)
+    from paper_2106_06889_amd import autotune
+    key = f"{autotune.arch()}/batch_word_count/{autotune.size_bucket(totT // len(pairs))}"
+    tuned = autotune.apply(ctx, key)
+    if not tuned:
+        res = autotune.tune_batch_word_count(ctx, loaded[:: max(1, len(loaded) // 32)], reps=3)
+        autotune.save(key, res)
+        tuned = autotune.apply(ctx, key)
+    params = {name: ctx.get_param(p) for p, name in autotune.NAMES.items()}
+    log(f"batched word count parameters ({'cache' if tuned else 'defaults'}): {params}")
     srv = serve.Server(ctx, loaded, max_batch=args.max_batch)
+    t1 = time.time()
+    srv.prepare()  # per-grammar query footprints (admission by memory)
+    log(f"query footprints measured in {time.time() - t1:.1f}s")
     # warm up every query kind once on a few grammars
     srv.run(serve.poisson_trace(64, 0, len(loaded), seed=1), realtime=False)
     srv.run_plain(serve.poisson_trace(32, 0, len(loaded), seed=2), realtime=False)
@@ -618,6 +649,7 @@ def run_serve(args):
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"{len(pairs)} resident grammars, sizes log-uniform 1e4-2e7 tokens x{args.scale}, "
                                f"sum T = {totT}; queries 50% word count, 30% term vector, 20% bigram count",
+                   "queries_per_trace": args.queries, "batched_word_count_params": params,
                    "max_batch": args.max_batch, "plain_capacity_qps": cap_plain,
                    "served_words_per_s": cap * mean_T},
         "latency": loads,
@@ -636,8 +668,9 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the workload (testing only)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds for the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch parameters")
     ap.add_argument("--grammars", type=int, default=256, help="serve: resident grammars")
-    ap.add_argument("--queries", type=int, default=2000, help="serve: queries per trace")
+    ap.add_argument("--queries", type=int, default=20000, help="serve: queries per trace")
     ap.add_argument("--max-batch", type=int, default=64, help="serve: word counts per batch")
     ap.add_argument("--workers", type=int, default=16, help="serve: host processes generating grammars")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -112,7 +112,10 @@ int gtadoc_ctx_usage(gtadoc_ctx ctx, uint64_t* in_use, uint64_t* peak, uint64_t*
  * weight(p)). Blocks until the load has finished on `stream` (it reads back
  * the validation status and the level structure). Host inputs may be freed
  * on return; copied device inputs once the call has returned.
- * Errors: INVALID_ARG, BAD_GRAMMAR, CYCLE, OOM, HIP. */
+ * Errors: INVALID_ARG, BAD_GRAMMAR, CYCLE, OOM, HIP; UNSUPPORTED when a rule
+ * occurs 2^40 or more times in the text or is referenced 2^24 or more times
+ * by other rules (the load keeps a rule's weight and pending in-edges in one
+ * 64-bit word). */
 int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t num_rules, const int32_t* sym,
                         int64_t num_sym, const int64_t* file_off, int64_t num_files, int32_t vocab,
                         uint32_t flags, void* stream, gtadoc_grammar* out);
@@ -243,6 +246,16 @@ int gtadoc_ranked_inverted_index_from_tv(gtadoc_grammar g, gtadoc_result term_ve
  * >= 2^16), OVERFLOW, OOM, HIP. */
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream);
 
+/* Sequence count for any length n in 2..8 with wide keys (Section "Sequence
+ * Support": sequences of a general length; head and tail buffers of up to 7
+ * words per rule). The n-gram's words, b = bits of (vocab - 1) each, are
+ * packed big-endian into a number of n * b <= 126 bits, split into the upper
+ * and lower 63 bits (hi, lo), so ascending (hi, lo) is lexicographic n-gram
+ * order. Result arrays: [0] uint64 hi[U], [1] uint64 lo[U], [2] uint64
+ * count[U], ascending (hi, lo). Synchronizes `stream`. Errors: INVALID_ARG
+ * (n outside 2..8), UNSUPPORTED (n * b > 126), OOM, OVERFLOW, HIP. */
+int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void* stream);
+
 /* ---- tunables (read by the autotuner; per context) ---------------------- */
 #define GTADOC_PARAM_WC_CHUNK 1          /* word-count reduce: entries per work item (>= 1024) */
 #define GTADOC_PARAM_BATCH_BLOCKS_PER_CU 2  /* batched word count: persistent scatter workgroups per CU */
@@ -251,6 +264,11 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
 #define GTADOC_PARAM_TIMING 4          /* 1: record HIP events around the main kernels of every call */
 #define GTADOC_PARAM_LEVEL_WIDE 5      /* load: levels of at least this many rules accumulate weights and
                                           in-edges by bucket instead of atomics (0: never; default 262144) */
+#define GTADOC_PARAM_LEVEL_LONG_BODY 6  /* load: rule bodies longer than this are walked by a whole
+                                          wave (the thread-group threshold for long rules); default 32 */
+#define GTADOC_PARAM_LEVEL_MID_RULES 7  /* load: levels narrower than this run on MID_BLOCKS workgroups */
+#define GTADOC_PARAM_LEVEL_MID_BLOCKS 8 /* load: workgroups of the narrower levels (1..256); default 32 */
+#define GTADOC_PARAM_LEVEL_TAIL_RULES 9 /* load: levels narrower than this run on one workgroup; default 1024 */
 
 /* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);

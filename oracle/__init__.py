@@ -72,6 +72,8 @@ def _load():
             "or_head_tail": (ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.c_int, _vp, _vp]),
             "or_owned_counts": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int, _vp]),
             "or_sc_traverse": (_i64, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int, _i32, _vp, _vp]),
+            "or_sc_text_wide": (_i64, [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, _vp, _vp]),
+            "or_sc_traverse_wide": (_i64, [_vp, _i64, _vp, _vp, _i64, ctypes.c_int, _i32, _vp, _vp, _vp]),
             "or_check_sequitur": (ctypes.c_int, [_vp, _i64, _vp, _vp, _i64]),
         }
         for name, (res, args) in sig.items():
@@ -218,6 +220,48 @@ def sc_text(tokens: np.ndarray, file_off: np.ndarray, n: int, vocab: int):
     u = _check(_load().or_sc_text(_p(tokens), _p(file_off), len(file_off) - 1, n, vocab, ctypes.byref(pk),
                                   ctypes.byref(pc)), "sc_text")
     return _take(pk, u, np.uint64), _take(pc, u, np.uint64)
+
+
+def wide_bits(vocab: int) -> int:
+    """Bits per word of the wide keys: the bits of vocab - 1 (at least 1)."""
+    return max(1, int(vocab - 1).bit_length())
+
+
+def sc_text_wide(tokens: np.ndarray, file_off: np.ndarray, n: int, vocab: int):
+    """Sequence count with wide keys (n <= 8, n * wide_bits(vocab) <= 126):
+    ascending (hi uint64[U], lo uint64[U], count uint64[U]); the n-gram is the
+    big-endian packing of its words, wide_bits(vocab) bits each, split into
+    63-bit halves hi and lo."""
+    tokens = np.ascontiguousarray(tokens, dtype=np.int32)
+    file_off = np.ascontiguousarray(file_off, dtype=np.int64)
+    ph, pl, pc = _vp(), _vp(), _vp()
+    u = _check(_load().or_sc_text_wide(_p(tokens), _p(file_off), len(file_off) - 1, n, vocab, ctypes.byref(ph),
+                                       ctypes.byref(pl), ctypes.byref(pc)), "sc_text_wide")
+    return _take(ph, u, np.uint64), _take(pl, u, np.uint64), _take(pc, u, np.uint64)
+
+
+def traverse_sequence_count_wide(g, n: int):
+    """Sequence count with wide keys by traversal (head/tail buffers, owned
+    windows weighted by rule weights); same layout as sc_text_wide."""
+    ro, sym, fo, R, F = _grammar(g)
+    ph, pl, pc = _vp(), _vp(), _vp()
+    u = _check(_load().or_sc_traverse_wide(_p(ro), R, _p(sym), _p(fo), F, n, int(g.vocab), ctypes.byref(ph),
+                                           ctypes.byref(pl), ctypes.byref(pc)), "sc_traverse_wide")
+    return _take(ph, u, np.uint64), _take(pl, u, np.uint64), _take(pc, u, np.uint64)
+
+
+def unpack_wide(hi: np.ndarray, lo: np.ndarray, n: int, vocab: int) -> np.ndarray:
+    """The n-grams of wide keys as rows of word ids (int64[U, n])."""
+    b = wide_bits(vocab)
+    words = np.empty((len(hi), n), dtype=np.int64)
+    h = hi.astype(object)
+    l = lo.astype(object)
+    v = [(int(a) << 63) | int(c) for a, c in zip(h, l)]
+    mask = (1 << b) - 1
+    for j in range(n):
+        shift = b * (n - 1 - j)
+        words[:, j] = [(x >> shift) & mask for x in v]
+    return words
 
 
 # --------------------------------------------------------- (A) brute force

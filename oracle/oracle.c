@@ -636,24 +636,51 @@ int or_head_tail(const int64_t* rule_off, int64_t R, const int32_t* sym, const u
  * number of windows, or < 0 on error. */
 typedef struct {
   uint64_t* key;
+  uint64_t* key2; /* low half of a wide key (wide_b > 0), else unused */
   uint64_t* wt;
   int64_t m, cap;
+  int wide_b;     /* 0: keys packed by pack_key; b > 0: wide keys, b bits per word */
 } or_pairs;
 
-static int push_pair(or_pairs* p, uint64_t k, uint64_t w) {
+static int push_pair2(or_pairs* p, uint64_t k, uint64_t k2, uint64_t w) {
   if (p->m == p->cap) {
     int64_t cap = p->cap ? p->cap * 2 : 1024;
-    uint64_t* k2 = realloc(p->key, sizeof(uint64_t) * (size_t)cap);
-    if (k2) p->key = k2;
-    uint64_t* w2 = realloc(p->wt, sizeof(uint64_t) * (size_t)cap);
-    if (w2) p->wt = w2;
-    if (!k2 || !w2) return OR_ERR_NOMEM;
+    uint64_t* a = realloc(p->key, sizeof(uint64_t) * (size_t)cap);
+    if (a) p->key = a;
+    uint64_t* b = realloc(p->key2, sizeof(uint64_t) * (size_t)cap);
+    if (b) p->key2 = b;
+    uint64_t* c = realloc(p->wt, sizeof(uint64_t) * (size_t)cap);
+    if (c) p->wt = c;
+    if (!a || !b || !c) return OR_ERR_NOMEM;
     p->cap = cap;
   }
   p->key[p->m] = k;
+  p->key2[p->m] = k2;
   p->wt[p->m] = w;
   ++p->m;
   return OR_OK;
+}
+
+static int push_pair(or_pairs* p, uint64_t k, uint64_t w) { return push_pair2(p, k, 0, w); }
+
+/* Wide keys, for n-grams whose packed form does not fit 64 bits: the words
+ * are packed big-endian with b bits each (b = bits of vocab - 1) into a
+ * number of at most 126 bits, split into two 63-bit halves hi and lo, so
+ * ascending (hi, lo) is lexicographic n-gram order. */
+static void pack_wide(const int32_t* g, int n, int b, uint64_t* hi, uint64_t* lo) {
+  const uint64_t m63 = (1ull << 63) - 1;
+  uint64_t h = 0, l = 0;
+  for (int i = 0; i < n; ++i) {
+    h = ((h << b) | (l >> (63 - b))) & m63;
+    l = ((l << b) | (uint32_t)g[i]) & m63;
+  }
+  *hi = h, *lo = l;
+}
+
+static int bits_of(int32_t V) {
+  int b = 0;
+  while (b < 31 && ((int64_t)1 << b) < (int64_t)V) ++b;
+  return b > 0 ? b : 1;
 }
 
 static int64_t owned_windows(const int64_t* rule_off, const int32_t* sym, const uint64_t* len,
@@ -700,7 +727,15 @@ static int64_t owned_windows(const int64_t* rule_off, const int32_t* sym, const 
       if (piece[a + j] < 0 || piece[a + j] != piece[a]) inside = 0;
     }
     if (gap || inside) continue;
-    if (out && push_pair(out, pack_key(seq + a, n), weight) != OR_OK) {
+    int prc = OR_OK;
+    if (out && out->wide_b > 0) {
+      uint64_t hi, lo;
+      pack_wide(seq + a, n, out->wide_b, &hi, &lo);
+      prc = push_pair2(out, hi, lo, weight);
+    } else if (out) {
+      prc = push_pair(out, pack_key(seq + a, n), weight);
+    }
+    if (prc != OR_OK) {
       free(seq), free(piece);
       return OR_ERR_NOMEM;
     }
@@ -759,7 +794,7 @@ int64_t or_sc_traverse(const int64_t* rule_off, int64_t R, const int32_t* sym, c
   uint64_t* w = malloc(sizeof(uint64_t) * (size_t)R);
   int32_t* head = malloc(sizeof(int32_t) * hs);
   int32_t* tail = malloc(sizeof(int32_t) * hs);
-  or_pairs P = {0, 0, 0, 0};
+  or_pairs P = {0, 0, 0, 0, 0, 0};
   int64_t rc = (!len || !w || !head || !tail) ? OR_ERR_NOMEM : or_rule_len(rule_off, R, sym, len);
   if (rc == OR_OK) rc = or_head_tail(rule_off, R, sym, len, n, head, tail);
   if (rc == OR_OK) rc = or_weights(rule_off, R, sym, w);
@@ -793,8 +828,92 @@ int64_t or_sc_traverse(const int64_t* rule_off, int64_t R, const int32_t* sym, c
       *key_out = k, *cnt_out = c;
     }
   }
-  free(len), free(w), free(head), free(tail), free(P.key), free(P.wt);
+  free(len), free(w), free(head), free(tail), free(P.key), free(P.key2), free(P.wt);
   return rc < 0 ? rc : u;
+}
+
+/* ---- wide keys (any n up to 8, n * bits(vocab - 1) <= 126) ---- */
+
+static const uint64_t* g_wk_hi;
+static const uint64_t* g_wk_lo;
+static int cmp_wide(const void* a, const void* b) {
+  int64_t i = *(const int64_t*)a, j = *(const int64_t*)b;
+  if (g_wk_hi[i] != g_wk_hi[j]) return g_wk_hi[i] < g_wk_hi[j] ? -1 : 1;
+  if (g_wk_lo[i] != g_wk_lo[j]) return g_wk_lo[i] < g_wk_lo[j] ? -1 : 1;
+  return 0;
+}
+
+/* Merge weighted wide keys into ascending (hi, lo, count) by sorting. */
+static int64_t wide_runs(const or_pairs* P, uint64_t** hi_out, uint64_t** lo_out, uint64_t** cnt_out) {
+  int64_t m = P->m;
+  int64_t* idx = malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+  uint64_t* h = malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+  uint64_t* l = malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+  uint64_t* c = malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+  if (!idx || !h || !l || !c) {
+    free(idx), free(h), free(l), free(c);
+    return OR_ERR_NOMEM;
+  }
+  for (int64_t i = 0; i < m; ++i) idx[i] = i;
+  g_wk_hi = P->key, g_wk_lo = P->key2;
+  qsort(idx, (size_t)m, sizeof(int64_t), cmp_wide);
+  int64_t u = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    uint64_t a = P->key[idx[i]], b = P->key2[idx[i]], w = P->wt[idx[i]];
+    if (u > 0 && h[u - 1] == a && l[u - 1] == b) c[u - 1] += w;
+    else h[u] = a, l[u] = b, c[u] = w, ++u;
+  }
+  free(idx);
+  *hi_out = h, *lo_out = l, *cnt_out = c;
+  return u;
+}
+
+static int wide_args(int n, int32_t V) { return n >= 1 && n <= 8 && V >= 1 && n * bits_of(V) <= 126; }
+
+/* Sequence count with wide keys from the text: every window of every file. */
+int64_t or_sc_text_wide(const int32_t* tok, const int64_t* file_off, int64_t F, int n, int32_t V,
+                        uint64_t** hi_out, uint64_t** lo_out, uint64_t** cnt_out) {
+  if (!wide_args(n, V)) return OR_ERR_ARG;
+  or_pairs P = {0, 0, 0, 0, 0, bits_of(V)};
+  int64_t rc = OR_OK;
+  for (int64_t f = 0; f < F && rc == OR_OK; ++f)
+    for (int64_t i = file_off[f]; i + n <= file_off[f + 1] && rc == OR_OK; ++i) {
+      uint64_t hi, lo;
+      pack_wide(tok + i, n, P.wide_b, &hi, &lo);
+      rc = push_pair2(&P, hi, lo, 1);
+    }
+  int64_t u = rc == OR_OK ? wide_runs(&P, hi_out, lo_out, cnt_out) : rc;
+  free(P.key), free(P.key2), free(P.wt);
+  return u;
+}
+
+/* Sequence count with wide keys by traversal: head and tail buffers of n-1
+ * words, then every rule's owned windows weighted by the rule's weight (the
+ * root's per file span), as or_sc_traverse. */
+int64_t or_sc_traverse_wide(const int64_t* rule_off, int64_t R, const int32_t* sym, const int64_t* file_off,
+                            int64_t F, int n, int32_t V, uint64_t** hi_out, uint64_t** lo_out, uint64_t** cnt_out) {
+  if (!wide_args(n, V)) return OR_ERR_ARG;
+  size_t hs = (size_t)R * (size_t)(n > 1 ? n - 1 : 1);
+  uint64_t* len = malloc(sizeof(uint64_t) * (size_t)R);
+  uint64_t* w = malloc(sizeof(uint64_t) * (size_t)R);
+  int32_t* head = malloc(sizeof(int32_t) * hs);
+  int32_t* tail = malloc(sizeof(int32_t) * hs);
+  or_pairs P = {0, 0, 0, 0, 0, bits_of(V)};
+  int64_t rc = (!len || !w || !head || !tail) ? OR_ERR_NOMEM : or_rule_len(rule_off, R, sym, len);
+  if (rc == OR_OK) rc = or_head_tail(rule_off, R, sym, len, n, head, tail);
+  if (rc == OR_OK) rc = or_weights(rule_off, R, sym, w);
+  for (int64_t f = 0; f < F && rc >= 0; ++f) {
+    int64_t c = owned_windows(rule_off, sym, len, head, tail, n, file_off[f], file_off[f + 1], 1, &P);
+    if (c < 0) rc = c;
+  }
+  for (int64_t r = 1; r < R && rc >= 0; ++r) {
+    if (w[r] == 0) continue;
+    int64_t c = owned_windows(rule_off, sym, len, head, tail, n, rule_off[r], rule_off[r + 1], w[r], &P);
+    if (c < 0) rc = c;
+  }
+  int64_t u = rc >= 0 ? wide_runs(&P, hi_out, lo_out, cnt_out) : rc;
+  free(len), free(w), free(head), free(tail), free(P.key), free(P.key2), free(P.wt);
+  return u;
 }
 
 /* ------------------------------------------------------------------------ */

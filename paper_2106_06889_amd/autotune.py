@@ -3,10 +3,18 @@
 Following the paper's parameter selection (Section Fine-Grained Thread-Level
 Execution Engine, parameter selection): take a sample of the input and set
 the parameters greedily, one at a time, keeping the others fixed; without a
-sample, fall back to defaults. Here the tunables are the persistent scatter
-workgroups per CU of the batched word count and the reduce chunk; each
-candidate is timed with HIP events on the query stream. Results are cached in
-a JSON file keyed by (GPU architecture, query kind, size bucket).
+sample, fall back to defaults. Two groups of tunables, each searched
+greedily on its own:
+  * the batched word count: persistent scatter workgroups per CU and the
+    reduce chunk (timed on a sample batch of grammars);
+  * the load's level walk and the word count of one grammar: the bucketed
+    mode threshold, the thread-group threshold for long rule bodies (the
+    paper's "16 times the average elements per thread" rule), the width
+    below which levels run on fewer workgroups and how many, the width below
+    which one workgroup finishes, and the word-count reduce chunk (timed on a
+    sample grammar: load, then word count).
+Each candidate is timed with HIP events on the query stream. Results are
+cached in a JSON file keyed by (GPU architecture, query kind, size bucket).
 """
 from __future__ import annotations
 
@@ -25,7 +33,22 @@ CANDIDATES = {
     gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
 }
 DEFAULTS = {gt.PARAM_BATCH_BLOCKS_PER_CU: 4, gt.PARAM_WC_CHUNK: 32768}
-NAMES = {gt.PARAM_BATCH_BLOCKS_PER_CU: "batch_blocks_per_cu", gt.PARAM_WC_CHUNK: "wc_chunk"}
+NAMES = {gt.PARAM_BATCH_BLOCKS_PER_CU: "batch_blocks_per_cu", gt.PARAM_WC_CHUNK: "wc_chunk",
+         gt.PARAM_LEVEL_WIDE: "level_wide", gt.PARAM_LEVEL_LONG_BODY: "level_long_body",
+         gt.PARAM_LEVEL_MID_RULES: "level_mid_rules", gt.PARAM_LEVEL_MID_BLOCKS: "level_mid_blocks",
+         gt.PARAM_LEVEL_TAIL_RULES: "level_tail_rules"}
+
+# the load (level walk) and the single-grammar word count, in search order
+LOAD_CANDIDATES = {
+    gt.PARAM_LEVEL_WIDE: [0, 131072, 262144, 524288, 1 << 30],
+    gt.PARAM_LEVEL_MID_RULES: [16384, 32768, 49152, 98304],
+    gt.PARAM_LEVEL_MID_BLOCKS: [8, 16, 32, 64],
+    gt.PARAM_LEVEL_TAIL_RULES: [256, 1024, 4096, 8192],
+    gt.PARAM_LEVEL_LONG_BODY: [16, 32, 64, 128],
+    gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
+}
+LOAD_DEFAULTS = {gt.PARAM_LEVEL_WIDE: 262144, gt.PARAM_LEVEL_MID_RULES: 49152, gt.PARAM_LEVEL_MID_BLOCKS: 32,
+                 gt.PARAM_LEVEL_TAIL_RULES: 1024, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 32768}
 
 
 def arch() -> str:
@@ -72,6 +95,39 @@ def tune_batch_word_count(ctx: gt.Context, grammars, reps: int = 5, verbose: boo
         timings[NAMES[p]] = {str(k): v for k, v in scores.items()}
     plan.close()
     return {"params": {NAMES[p]: v for p, v in best.items()}, "timings_ms": timings}
+
+
+def greedy(ctx, candidates: dict, defaults: dict, run, reps: int, verbose: bool = False) -> dict:
+    """Set each parameter in turn to its fastest candidate (timing `run`),
+    the others fixed at their current best; leaves the best values set."""
+    best = dict(defaults)
+    for p, v in best.items():
+        ctx.set_param(p, v)
+    timings = {}
+    for p, cands in candidates.items():
+        scores = {}
+        for v in cands:
+            ctx.set_param(p, v)
+            scores[v] = _time(run, reps)
+            if verbose:
+                print(f"[autotune] {NAMES[p]}={v}: {scores[v] * 1e3:.1f} us", flush=True)
+        best[p] = min(scores, key=scores.get)
+        ctx.set_param(p, best[p])
+        timings[NAMES[p]] = {str(k): v for k, v in scores.items()}
+    return {"params": {NAMES[p]: v for p, v in best.items()}, "timings_ms": timings}
+
+
+def tune_load(ctx: gt.Context, rule_off, sym, file_off, vocab: int, reps: int = 3, verbose: bool = False) -> dict:
+    """Greedy search of the level walk's launch shape and the word-count
+    chunk on a sample grammar (device tensors, loaded by borrowing): each
+    candidate is timed over a load followed by a word count."""
+    out = torch.empty(vocab, dtype=torch.int64, device=ctx.device)
+
+    def run():
+        G = ctx.load(rule_off, sym, file_off, vocab, borrow=True)
+        G.word_count(out)
+        G.free()
+    return greedy(ctx, LOAD_CANDIDATES, LOAD_DEFAULTS, run, reps, verbose)
 
 
 def load_cache() -> dict:

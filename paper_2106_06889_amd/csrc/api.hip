@@ -146,6 +146,7 @@ struct gtadoc_ctx_s {
   int64_t param_epoch = 0;       // bumped on every parameter change (invalidates captured graphs)
   int64_t timing = 0;            // record events around the main kernels of each call
   int64_t level_wide = 262144;   // level walk: bucketed mode from this many rules per level (0: never)
+  gt::LevelParams level;         // level walk launch shape
   struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;  // recorded, not yet read
     std::vector<hipEvent_t> spare;
@@ -185,6 +186,10 @@ struct gtadoc_grammar_s {
   uint64_t* seq_len = nullptr;
   int32_t* seq_head = nullptr;
   int32_t* seq_tail = nullptr;
+  // head/tail/len buffers of up to 7 words for the wide-key sequence count
+  uint64_t* seqw_len = nullptr;
+  int32_t* seqw_head = nullptr;
+  int32_t* seqw_tail = nullptr;
   std::map<int64_t, uint64_t> footprint;  // arena bytes of a query kind (gtadoc_query_bytes)
   int64_t edges = -1;                     // distinct (parent, child) pairs (gtadoc_grammar_edges)
 };
@@ -446,13 +451,12 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   const int64_t n_rc_off = (int64_t)d.rc_nb * d.nslot;
   d.wc_off = d.wc_nb ? call.keep<uint32_t>(n_wc_off, g->blocks) : nullptr;
   d.rc_off = d.rc_nb ? call.scratch<uint32_t>(n_rc_off) : nullptr;
-  int32_t* pend = call.scratch<int32_t>(R);
   int32_t* level_cnt = call.scratch<int32_t>(R + 2);
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
   uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
                                                     nbR + gt::scan_scratch_entries(nbR) + 2}));
-  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !pend || !level_cnt || !lc || !sums ||
+  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !level_cnt || !lc || !sums ||
       (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));
   d.tile_rule = tile_rule;
@@ -501,11 +505,10 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   PhaseScope t_load(ctx, GTADOC_PHASE_LOAD, s);
   const bool atomic_degrees = d.rc_nb == 0;
   if (!hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
-      (atomic_degrees && (!hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill") ||
-                          !hip_ok(gt::launch_fill_i32(pend, R, 0, s), "fill"))) ||
+      (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill")) ||
       (n_wc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
       (n_rc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
-      !hip_ok(gt::launch_scan_symbols(d, pend, lc, s), "scan_symbols") ||
+      !hip_ok(gt::launch_scan_symbols(d, lc, s), "scan_symbols") ||
       (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
       (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
       (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, 1, 1, s), "fill")))
@@ -514,17 +517,18 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     // one entry per rule reference: at most S of them (the exact count stays on the device)
     uint16_t* ref_entries = call.scratch<uint16_t>(S);
     if (!ref_entries) return bail(oom("reference entries", 2 * (uint64_t)S));
-    if (!hip_ok(gt::launch_in_degrees(d, pend, ref_entries, &lc->rc_entries, s), "in_degrees"))
+    if (!hip_ok(gt::launch_in_degrees(d, ref_entries, &lc->rc_entries, lc, s), "in_degrees"))
       return bail(GTADOC_ERR_HIP);
   }
-  if (!hip_ok(gt::launch_level_frontier(d, pend, lc, sums, s), "levels"))
+  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s), "levels"))
     return bail(GTADOC_ERR_HIP);
-  if (!hip_ok(gt::prepare_level_walk(d, pend, lc, sums, wide, s), "levels"))
+  if (!hip_ok(gt::prepare_level_walk(d, lc, sums, wide, s), "levels"))
     return bail(GTADOC_ERR_HIP);
   PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);  // the level walk kernel alone
-  if (!hip_ok(gt::launch_level_walk(d, pend, level_cnt, lc, sums, wide, ctx->device, s), "levels"))
+  if (!hip_ok(gt::launch_level_walk(d, level_cnt, lc, sums, wide, ctx->level, ctx->device, s), "levels"))
     return bail(GTADOC_ERR_HIP);
   t_levels.end();
+  if (!hip_ok(gt::launch_unpack_weights(d, s), "weights")) return bail(GTADOC_ERR_HIP);
   t_load.end();
   // the counters and the first level offsets come back with one wait
   static_assert(sizeof(gt::LoadCounters) <= kPinnedLevelAt, "counters overlap the level offsets");
@@ -534,10 +538,13 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
       !hip_ok(hipMemcpyAsync(plevel, d.level_off, sizeof(int32_t) * nlev, hipMemcpyDeviceToHost, s), "read levels") ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
-  if (pc->status)
+  if (pc->status & (gt::ST_BAD_WORD | gt::ST_BAD_REF))
     return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s",
                      (pc->status & gt::ST_BAD_WORD) ? "word id >= vocab; " : "",
                      (pc->status & gt::ST_BAD_REF) ? "rule reference outside [1, R)" : ""));
+  if (pc->status & gt::ST_PACK)
+    return bail(fail(GTADOC_ERR_UNSUPPORTED, "a rule is used 2^40 or more times, or referenced 2^24 or more times by "
+                                             "other rules (the load packs weight and pending in-edges in 64 bits)"));
   if (d.wc_nb && pc->wc_entries != (int64_t)pc->word_syms)
     return bail(fail(GTADOC_ERR_HIP, "internal: word bucket histogram %lld != word symbols %llu",
                      (long long)pc->wc_entries, (unsigned long long)pc->word_syms));
@@ -1185,6 +1192,101 @@ int sequence_count_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* out) 
 }
 }  // namespace
 
+namespace {
+// Byte mask covering bits [0, nbits) of a 64-bit key.
+uint64_t low_bytes_mask(int nbits) {
+  uint64_t m = 0;
+  for (int x = 0; x * 8 < nbits && x < 8; ++x) m |= 1ull << x;
+  return m;
+}
+
+int sequence_count_wide_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* out) {
+  const gt::DevGrammar& d = g->d;
+  hipStream_t s = call.stream();
+  const int64_t R = d.R, S = d.S;
+  const int b = std::max(1, bitlen((uint64_t)(d.V - 1)));
+  if (n * b > 126)
+    return fail(GTADOC_ERR_UNSUPPORTED, "wide sequence keys hold 126 bits: n = %d words of %d bits do not fit", n, b);
+  if (!g->seqw_len) {  // initialization phase: buffers of up to 7 words, children first
+    std::vector<Block> kept;
+    auto* len = call.keep<uint64_t>(R, kept);
+    auto* head = call.keep<int32_t>(8 * R, kept);
+    auto* tail = call.keep<int32_t>(8 * R, kept);
+    if (!len || !head || !tail) {
+      release_all(g->ctx, kept);
+      return oom("wide head/tail buffers", 72ull * R);
+    }
+    hipError_t e = gt::launch_headtail_wide(d, g->level_off.data(), (int32_t)g->st.depth, len, head, tail, s);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      release_all(g->ctx, kept);
+      return fail(GTADOC_ERR_HIP, "wide head/tail: %s", hipGetErrorString(e));
+    }
+    g->blocks.insert(g->blocks.end(), kept.begin(), kept.end());
+    g->seqw_len = len, g->seqw_head = head, g->seqw_tail = tail;
+  }
+  // at most n-1 windows start at a body position: the table has more slots than distinct keys
+  const uint64_t bound = (uint64_t)(n - 1) * (uint64_t)S + 1;
+  uint64_t cap = 1024;
+  while (cap < bound) cap <<= 1;
+  auto* table = call.scratch<uint64_t>(4 * (int64_t)cap);
+  const int64_t nb = ((int64_t)cap + 4095) / 4096;
+  auto* cnt = call.scratch<uint32_t>(nb + gt::scan_scratch_entries(nb));
+  auto* flags = call.scratch<int64_t>(2);  // [0] distinct keys, [1] overflow flag
+  if (!table || !cnt || !flags) return oom("wide sequence table", 32 * cap);
+  HIP_TRY(gt::launch_fill_i32(reinterpret_cast<int32_t*>(flags), 4, 0, s));
+  PhaseScope t_win(g->ctx, GTADOC_PHASE_SEQ_WINDOWS, s);
+  HIP_TRY(gt::launch_seq_windows_wide(d, n, g->seqw_len, g->seqw_head, g->seqw_tail, b, table, cap,
+                                      reinterpret_cast<uint32_t*>(flags + 1), s));
+  t_win.end();
+  HIP_TRY(gt::launch_wocc_count(table, (int64_t)cap, cnt, flags, cnt + nb, s));
+  auto* pc = reinterpret_cast<int64_t*>(g->ctx->pinned);
+  HIP_TRY(hipMemcpyAsync(pc, flags, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (pc[1] & 0xffffffff) return fail(GTADOC_ERR_OVERFLOW, "wide sequence table full");
+  const int64_t U = pc[0];
+  gtadoc_result res = new_result(g->ctx);
+  if (!res) return fail(GTADOC_ERR_OOM, "host allocation failed");
+  auto* ohi = call.keep<uint64_t>(U, res->blocks);
+  auto* olo = call.keep<uint64_t>(U, res->blocks);
+  auto* ocnt = call.keep<uint64_t>(U, res->blocks);
+  uint64_t* k[3] = {call.scratch<uint64_t>(U), call.scratch<uint64_t>(U), call.scratch<uint64_t>(U)};
+  uint32_t* v[3] = {call.scratch<uint32_t>(U), call.scratch<uint32_t>(U), call.scratch<uint32_t>(U)};
+  auto* hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(U));
+  if (!ohi || !olo || !ocnt || !k[0] || !k[1] || !k[2] || !v[0] || !v[1] || !v[2] || !hist) {
+    release_all(g->ctx, res->blocks);
+    delete res;
+    return oom("wide sequence result", 60ull * U);
+  }
+  if (U > 0) {
+    const int total_bits = n * b;
+    const hipError_t e = gt::launch_wide_sort(table, (int64_t)cap, cnt, flags, U, low_bytes_mask(std::min(63, total_bits)),
+                                              low_bytes_mask(std::max(0, total_bits - 63)), k, v, hist, ohi, olo, ocnt, s);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      release_all(g->ctx, res->blocks);
+      delete res;
+      return fail(GTADOC_ERR_HIP, "wide sequence sort: %s", hipGetErrorString(e));
+    }
+  }
+  res->a[0] = {ohi, U, 8};
+  res->a[1] = {olo, U, 8};
+  res->a[2] = {ocnt, U, 8};
+  res->na = 3;
+  *out = res;
+  return GTADOC_OK;
+}
+}  // namespace
+
+int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
+  if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (n < 2 || n > 8) return fail(GTADOC_ERR_INVALID_ARG, "n must be in 2..8");
+  Call call(g->ctx, stream);
+  const int rc = call.begin();
+  if (rc) return rc;
+  return sequence_count_wide_run(g, n, call, out);
+}
+
 int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   int rc = sequence_args(g, n);
@@ -1216,6 +1318,22 @@ int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
       if (value < 0) return fail(GTADOC_ERR_INVALID_ARG, "level width threshold out of range");
       ctx->level_wide = value;
       return GTADOC_OK;  // read at load time only
+    case GTADOC_PARAM_LEVEL_LONG_BODY:
+      if (value < 1 || value > (1 << 20)) return fail(GTADOC_ERR_INVALID_ARG, "long-body threshold out of range");
+      ctx->level.long_body = (int32_t)value;
+      return GTADOC_OK;
+    case GTADOC_PARAM_LEVEL_MID_RULES:
+      if (value < 1 || value > INT32_MAX) return fail(GTADOC_ERR_INVALID_ARG, "mid-level threshold out of range");
+      ctx->level.mid_rules = (int32_t)value;
+      return GTADOC_OK;
+    case GTADOC_PARAM_LEVEL_MID_BLOCKS:
+      if (value < 1 || value > 256) return fail(GTADOC_ERR_INVALID_ARG, "mid-level workgroups out of range");
+      ctx->level.mid_blocks = (int32_t)value;
+      return GTADOC_OK;
+    case GTADOC_PARAM_LEVEL_TAIL_RULES:
+      if (value < 1 || value > INT32_MAX) return fail(GTADOC_ERR_INVALID_ARG, "tail-level threshold out of range");
+      ctx->level.tail_rules = (int32_t)value;
+      return GTADOC_OK;
     default:
       return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
@@ -1231,6 +1349,10 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value) {
     case GTADOC_PARAM_BATCH_GRAPH: *value = ctx->batch_graph; break;
     case GTADOC_PARAM_TIMING: *value = ctx->timing; break;
     case GTADOC_PARAM_LEVEL_WIDE: *value = ctx->level_wide; break;
+    case GTADOC_PARAM_LEVEL_LONG_BODY: *value = ctx->level.long_body; break;
+    case GTADOC_PARAM_LEVEL_MID_RULES: *value = ctx->level.mid_rules; break;
+    case GTADOC_PARAM_LEVEL_MID_BLOCKS: *value = ctx->level.mid_blocks; break;
+    case GTADOC_PARAM_LEVEL_TAIL_RULES: *value = ctx->level.tail_rules; break;
     default: return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
   return GTADOC_OK;

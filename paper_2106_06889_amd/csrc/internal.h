@@ -47,6 +47,15 @@ __host__ __device__ inline int64_t xcd_slot(int64_t blk, int64_t nslot) {
   return (blk % kXcds) * (nslot / kXcds) + blk / kXcds;
 }
 
+// During the load every rule's weight and its pending in-edges (references
+// from non-root bodies not yet applied) share one 64-bit word,
+// weight << kPendBits | pending, so that one atomic adds a parent's weight
+// and retires its in-edge, and its return value tells whether that was the
+// last one. The load unpacks the words into plain weights at the end.
+constexpr int kPendBits = 24;
+constexpr uint64_t kPendMask = (1ull << kPendBits) - 1;
+constexpr int kWeightBits = 64 - kPendBits;
+
 // Bits of the validation status word.
 enum : uint32_t {
   ST_BAD_OFFSETS = 1u,   // rule_off not monotone / not [0, S]
@@ -54,6 +63,7 @@ enum : uint32_t {
   ST_BAD_FILES = 4u,     // file spans do not tile the root body
   ST_BAD_WORD = 8u,      // word id >= vocab
   ST_BAD_REF = 16u,      // rule reference outside [1, R)
+  ST_PACK = 32u,         // a weight >= 2^40 or an in-degree >= 2^24 (beyond the packed load word)
 };
 
 // Device view of a loaded grammar and its initialization-phase products.
@@ -65,7 +75,7 @@ struct DevGrammar {
   int32_t V;
   int64_t ntiles;            // ceil(S / kTileSyms)
   const int32_t* tile_rule;  // [ntiles+1]: rule holding the first symbol of each tile; [ntiles] = R-1
-  uint64_t* w;               // [R] top-down weights, w[0] = 1
+  uint64_t* w;               // [R] top-down weights, w[0] = 1 (packed with pending in-edges during the load)
   int32_t* level_rule;       // [R-1] rules grouped by level (level 1 first)
   int32_t* level_off;        // [D+2] level d occupies level_rule[level_off[d] .. level_off[d+1]), d >= 1
   int64_t nblk;              // ceil(S / kBlockSyms)
@@ -123,16 +133,30 @@ hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int
                               LoadCounters* lc, hipStream_t s);
 hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc,
                               hipStream_t s);
-hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s);
-// in-degrees and initial weights from the reference entries (after the offsets are scanned)
-hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entries, const int64_t* n, hipStream_t s);
+hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_t s);
+// in-degrees and initial weights (packed in g.w) from the reference entries
+// (after the offsets are scanned)
+hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s);
 // level 1 (rules no rule references) by compaction, then the level walk
-hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
-                                 hipStream_t s);
-hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
-                              const WideBufs& wide, hipStream_t s);
-hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
-                             uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s);
+hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s);
+hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, const WideBufs& wide,
+                              hipStream_t s);
+// Launch shape of the level walk (context parameters, tunable):
+//  long_body   bodies longer than this are walked by a whole wave (the
+//              paper's thread-group threshold for long rules);
+//  mid_rules   levels narrower than this run on the first mid_blocks
+//              workgroups only (a cheaper barrier);
+//  tail_rules  levels narrower than this run on workgroup 0 alone.
+struct LevelParams {
+  int32_t long_body = 32;
+  int32_t mid_rules = 48 * 1024;
+  int32_t mid_blocks = 32;
+  int32_t tail_rules = 1024;
+};
+hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
+                             const WideBufs& wide, const LevelParams& params, int device, hipStream_t s);
+// after the walk: g.w[r] = weight of r (the pending fields are zero)
+hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s);
 
 // word count and sort
 hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics
@@ -231,6 +255,18 @@ hipError_t launch_expand_root(const DevGrammar& g, const uint64_t* pos, int64_t 
 hipError_t launch_expand_depth(const DevGrammar& g, const uint64_t* len, const int32_t* in_rule, const int64_t* in_off,
                                const unsigned long long* in_n, int64_t cap, int32_t* tokens, int32_t* out_rule,
                                int64_t* out_off, unsigned long long* out_n, hipStream_t s);
+
+// sequence count with wide keys (any n <= 8; key = (hi, lo) 63-bit halves)
+hipError_t launch_headtail_wide(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
+                                int32_t* head, int32_t* tail, hipStream_t s);
+hipError_t launch_seq_windows_wide(const DevGrammar& g, int n, const uint64_t* len, const int32_t* head,
+                                   const int32_t* tail, int b, uint64_t* table, uint64_t cap, uint32_t* overflow,
+                                   hipStream_t s);
+hipError_t launch_wocc_count(const uint64_t* table, int64_t cap, uint32_t* cnt, int64_t* total, uint32_t* sums,
+                             hipStream_t s);
+hipError_t launch_wide_sort(const uint64_t* table, int64_t cap, const uint32_t* off, const int64_t* num, int64_t U,
+                            uint64_t lo_mask, uint64_t hi_mask, uint64_t* const* k, uint32_t* const* v,
+                            uint32_t* hist, uint64_t* out_hi, uint64_t* out_lo, uint64_t* out_cnt, hipStream_t s);
 
 // sequence count
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,

@@ -17,7 +17,10 @@
 // (short) or one wave (long), and the widest levels can accumulate by
 // bucket instead of atomics. In-degrees count occurrences (a rule used twice
 // by the same parent waits for both), which gives the same levels and
-// weights.
+// weights. A rule's weight and its pending in-edges share one 64-bit word
+// (weight << kPendBits | pending) during the walk: one atomic adds a
+// parent's weight and retires the in-edge, and its return value tells the
+// last parent that the rule is ready.
 #include "device.h"
 #include "radix.h"
 
@@ -26,13 +29,13 @@ namespace gt {
 // Level 1 = the rules with no pending in-edge (used only by the root, or not
 // at all), compacted in rule-id order: a count per block of kBlockSyms rules,
 // an exclusive scan, then every block writes its rules at its offset.
-__global__ __launch_bounds__(256) void k_zero_count(const int32_t* pend, int64_t R, uint32_t* cnt) {
+__global__ __launch_bounds__(256) void k_zero_count(const uint64_t* pw, int64_t R, uint32_t* cnt) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t r = i0 + k;
-    if (r >= 1 && r < R && pend[r] == 0) ++c;
+    if (r >= 1 && r < R && (pw[r] & kPendMask) == 0) ++c;
   }
   __shared__ uint32_t lds[4];
   uint32_t total;
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(256) void k_zero_count(const int32_t* pend, int64_t
   if (threadIdx.x == 0) cnt[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(256) void k_zero_write(const int32_t* pend, int64_t R, const uint32_t* off,
+__global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t R, const uint32_t* off,
                                                     int32_t* out) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
   uint32_t c = 0;
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(256) void k_zero_write(const int32_t* pend, int64_t
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t r = i0 + k;
-    z[k] = r >= 1 && r < R && pend[r] == 0;
+    z[k] = r >= 1 && r < R && (pw[r] & kPendMask) == 0;
     c += z[k];
   }
   __shared__ uint32_t lds[4];
@@ -78,7 +81,6 @@ constexpr int kLevelList = 8192;
 constexpr int kAggBits = 12;
 constexpr int kAggSlots = 1 << kAggBits;
 constexpr int kAggProbes = 8;
-constexpr int kLongBody = 32;                  // longer bodies are walked by a whole wave
 constexpr int kLongList = 4 * kLevelThreads;   // rules per workgroup and sub-round of a level
 
 struct LevelLds {
@@ -165,9 +167,6 @@ __device__ __forceinline__ void group_barrier(uint32_t* bar, uint32_t nblocks, u
   __syncthreads();
 }
 
-// Levels narrower than kMidRules run on the first kMidBlocks workgroups.
-constexpr int kMidBlocks = 32;
-constexpr int32_t kMidRules = 48 * 1024;
 
 // The workgroup's list of level d+1 goes after hi with one global atomic.
 __device__ __forceinline__ void level_list_out(DevGrammar& g, int32_t* level_cnt, LevelLds& L, int32_t d, int32_t hi) {
@@ -187,22 +186,22 @@ __device__ __forceinline__ void level_list_out(DevGrammar& g, int32_t* level_cnt
 // Walks the bodies of the rules level_rule[lo, hi) shared by `nthreads`
 // threads (this one is `tid`), calling op.begin(weight of p), op.sym(s) for
 // each body symbol and op.end() per rule. Short bodies are walked by one thread with 8
-// symbols loaded at a time; bodies longer than kLongBody are queued in LDS
+// symbols loaded at a time; bodies longer than lp.long_body are queued in LDS
 // and walked by a whole wave, lanes across the body, so one long rule never
 // holds a wave for hundreds of dependent loads. A level is taken in
 // sub-rounds of at most kLongList rules per workgroup, so the queue never
 // overflows.
 template <class Op>
 __device__ __forceinline__ void walk_bodies(const DevGrammar& g, LevelLds& L, int32_t lo, int32_t hi, int64_t tid,
-                                            int64_t nthreads, Op& op) {
+                                            int64_t nthreads, int32_t long_body, Op& op) {
   const int64_t span = (int64_t)(kLongList / kLevelThreads) * nthreads;
   for (int64_t base = lo; base < hi; base += span) {
     const int64_t end = base + span < hi ? base + span : hi;
     for (int64_t i = base + tid; i < end; i += nthreads) {
       const int32_t p = g.level_rule[i];
       const int64_t a = g.rule_off[p], e = g.rule_off[p + 1];
-      const uint64_t wp = g.w[p];  // issued with the offsets, not after them
-      if (e - a > kLongBody) {
+      const uint64_t wp = g.w[p] >> kPendBits;  // final (no pending in-edge); issued with the offsets
+      if (e - a > long_body) {
         L.longs[atomicAdd(&L.nlong, 1)] = p;
         continue;
       }
@@ -222,7 +221,7 @@ __device__ __forceinline__ void walk_bodies(const DevGrammar& g, LevelLds& L, in
     for (int j = threadIdx.x >> 6; j < nl; j += kLevelThreads >> 6) {
       const int32_t p = L.longs[j];
       const int64_t e = g.rule_off[p + 1];
-      op.begin(g.w[p]);
+      op.begin(g.w[p] >> kPendBits);
       int64_t q = g.rule_off[p] + lane_id();
       int32_t cur = q < e ? g.sym[q] : 0;
       for (; q < e; q += 64) {
@@ -241,9 +240,19 @@ __device__ __forceinline__ void walk_bodies(const DevGrammar& g, LevelLds& L, in
 // Per-symbol work of the atomic mode: the referencing rule's weight goes to
 // the sub-rule (merged in LDS when possible) and one of its in-edges
 // retires; a sub-rule whose last in-edge retires joins level d+1.
+// Adds weight dw and retires dn in-edges of rule c (one packed atomic);
+// true when these were its last pending in-edges. A weight carried past the
+// packed field sets ST_PACK.
+__device__ __forceinline__ bool retire(uint64_t* w, int32_t c, uint64_t dw, uint32_t dn, uint32_t* status) {
+  const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&w[c]),
+                                 (unsigned long long)((dw << kPendBits) - dn));
+  if ((old >> kPendBits) + dw >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
+  return (old & kPendMask) == dn;
+}
+
 struct AtomicOp {
   DevGrammar& g;
-  int32_t* pend;
+  uint32_t* status;
   int32_t* level_cnt;
   LevelLds& L;
   int32_t d, hi;
@@ -258,10 +267,7 @@ struct AtomicOp {
     } else if (-(int64_t)s < g.R) {
       // out-of-range ids are reported by the scan and never touched here
       c = (int32_t)(-(int64_t)s);
-      if (!agg_add(L, c, wp)) {
-        if (wp) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)wp);
-        ready = atomicSub(&pend[c], 1) == 1;
-      }
+      if (!agg_add(L, c, wp)) ready = retire(g.w, c, wp, 1u, status);
     }
     level_append(ready, c, L, g, level_cnt, d, hi);
   }
@@ -271,25 +277,30 @@ struct AtomicOp {
 // One level in the atomic mode: rules level_rule[lo, hi) processed by
 // `nthreads` threads (this one is `tid`); new members of level d+1 are
 // appended after hi.
-__device__ __forceinline__ void level_round(DevGrammar& g, int32_t* pend, int32_t* level_cnt, LevelLds& L, int32_t lo,
-                                            int32_t hi, int32_t d, int64_t tid, int64_t nthreads, uint64_t& tokens) {
-  AtomicOp op{g, pend, level_cnt, L, d, hi, tokens};
-  walk_bodies(g, L, lo, hi, tid, nthreads, op);
-  // apply the merged contributions
-  for (int slot = threadIdx.x; slot < kAggSlots; slot += blockDim.x) {
-    const int32_t c = L.u.agg.key[slot];
-    bool ready = false;
-    if (c >= 0) {
-      const uint64_t dw = L.u.agg.wsum[slot];
-      const int32_t dn = (int32_t)L.u.agg.cnt[slot];
-      if (dw) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)dw);
-      ready = atomicSub(&pend[c], dn) == dn;
+__device__ __forceinline__ void level_round(DevGrammar& g, const LevelParams& lp, uint32_t* status, int32_t* level_cnt,
+                                            LevelLds& L, int32_t lo, int32_t hi, int32_t d, int64_t tid,
+                                            int64_t nthreads, uint64_t& tokens) {
+  AtomicOp op{g, status, level_cnt, L, d, hi, tokens};
+  walk_bodies(g, L, lo, hi, tid, nthreads, lp.long_body, op);
+  // apply the merged contributions: all of the thread's atomics are issued
+  // before any result is used, so their round trips overlap
+  constexpr int kPer = kAggSlots / kLevelThreads;
+  int32_t cs[kPer];
+  bool ready[kPer];
+#pragma unroll
+  for (int x = 0; x < kPer; ++x) {
+    const int slot = (int)threadIdx.x + x * kLevelThreads;
+    cs[x] = L.u.agg.key[slot];
+    ready[x] = false;
+    if (cs[x] >= 0) {
+      ready[x] = retire(g.w, cs[x], L.u.agg.wsum[slot], L.u.agg.cnt[slot], status);
       L.u.agg.key[slot] = -1;
       L.u.agg.wsum[slot] = 0;
       L.u.agg.cnt[slot] = 0;
     }
-    level_append(ready, c, L, g, level_cnt, d, hi);
   }
+#pragma unroll
+  for (int x = 0; x < kPer; ++x) level_append(ready[x], cs[x], L, g, level_cnt, d, hi);
   level_list_out(g, level_cnt, L, d, hi);
 }
 
@@ -340,19 +351,19 @@ struct WriteOp {  // bucketed mode, second pass: one entry per reference
   __device__ void end() {}
 };
 
-__device__ __forceinline__ void wide_scatter(DevGrammar& g, const WideBufs& wb, LevelLds& L, int32_t lo, int32_t hi,
-                                             int64_t tid, int64_t nthreads, uint64_t& tokens) {
+__device__ __forceinline__ void wide_scatter(DevGrammar& g, const LevelParams& lp, const WideBufs& wb, LevelLds& L,
+                                             int32_t lo, int32_t hi, int64_t tid, int64_t nthreads, uint64_t& tokens) {
   for (int k = threadIdx.x; k < wb.nbk; k += blockDim.x) L.u.hist[k] = 0;
   __syncthreads();
   CountOp count{g, L, tokens, (uint32_t)(wb.nbk - 1)};
-  walk_bodies(g, L, lo, hi, tid, nthreads, count);
+  walk_bodies(g, L, lo, hi, tid, nthreads, lp.long_body, count);
   for (int k = threadIdx.x; k < wb.nbk; k += blockDim.x) {
     const uint32_t h = L.u.hist[k];
     if (h) L.u.hist[k] = atomicAdd(&wb.cur[k], h);
   }
   __syncthreads();
   WriteOp write{g, wb, L};
-  walk_bodies(g, L, lo, hi, tid, nthreads, write);
+  walk_bodies(g, L, lo, hi, tid, nthreads, lp.long_body, write);
 }
 
 // Bucketed mode, second half: each bucket's new entries are summed in a
@@ -360,7 +371,7 @@ __device__ __forceinline__ void wide_scatter(DevGrammar& g, const WideBufs& wb, 
 // owns the bucket, which then applies weight and retired in-edges to every
 // referenced rule with plain read-modify-writes (no other workgroup touches
 // the bucket's rules) and lists the rules whose last in-edge retired.
-__device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_t* level_cnt, const WideBufs& wb,
+__device__ __forceinline__ void wide_reduce(DevGrammar& g, uint32_t* status, int32_t* level_cnt, const WideBufs& wb,
                                             LevelLds& L, int32_t d, int32_t hi) {
   for (int32_t b = blockIdx.x; b < wb.nbk; b += gridDim.x) {
     if (threadIdx.x == 0) L.seg[0] = wb.seg_lo[b], L.seg[1] = wb.cur[b];
@@ -382,10 +393,11 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
         const int32_t c = (int32_t)(((uint32_t)k << wb.nbk_bits) | (uint32_t)b);
         bool ready = false;
         if (n) {
-          g.w[c] += L.u.dense.wsum[k];
-          const int32_t left = pend[c] - (int32_t)n;
-          pend[c] = left;
-          ready = left == 0;
+          const uint64_t old = g.w[c], dw = L.u.dense.wsum[k];
+          const uint64_t now = old + ((dw << kPendBits) - n);
+          if ((old >> kPendBits) + dw >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
+          g.w[c] = now;
+          ready = (now & kPendMask) == 0;
         }
         level_append(ready, c, L, g, level_cnt, d, hi);
       }
@@ -398,10 +410,10 @@ __device__ __forceinline__ void wide_reduce(DevGrammar& g, int32_t* pend, int32_
 
 // Levels narrower than this finish on workgroup 0 alone (block barriers
 // instead of grid barriers); the other workgroups leave.
-constexpr int32_t kTailRules = kLevelThreads;
 
-__global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* pend, int32_t* level_cnt,
-                                                          LoadCounters* lc, WideBufs wb, uint32_t* bar) {
+__global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t* level_cnt, LoadCounters* lc,
+                                                          WideBufs wb, LevelParams lp, uint32_t* bar) {
+  uint32_t* status = &lc->status;
   __shared__ LevelLds L;
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
@@ -414,16 +426,16 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   bool agg_clean = true;
   uint32_t gen = 0;  // barrier generation (the barrier words are zero at launch)
   // wide levels: the whole grid, a grid barrier between levels
-  const bool shrink = gridDim.x > (unsigned)kMidBlocks;
-  while (lo < hi && (hi - lo >= (shrink ? kMidRules : kTailRules) || gridDim.x == 1)) {
+  const bool shrink = gridDim.x > (unsigned)lp.mid_blocks;
+  while (lo < hi && (hi - lo >= (shrink ? lp.mid_rules : lp.tail_rules) || gridDim.x == 1)) {
     if (wb.ew && hi - lo >= wb.min_rules) {
-      wide_scatter(g, wb, L, lo, hi, tid, nthreads, tokens);
+      wide_scatter(g, lp, wb, L, lo, hi, tid, nthreads, tokens);
       group_barrier(bar, gridDim.x, gen);
-      wide_reduce(g, pend, level_cnt, wb, L, d, hi);
+      wide_reduce(g, status, level_cnt, wb, L, d, hi);
       agg_clean = false;
     } else {
       if (!agg_clean) agg_reset(L), agg_clean = true;
-      level_round(g, pend, level_cnt, L, lo, hi, d, tid, nthreads, tokens);
+      level_round(g, lp, status, level_cnt, L, lo, hi, d, tid, nthreads, tokens);
     }
     group_barrier(bar, gridDim.x, gen);
     const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -435,14 +447,14 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
     hi += next;
     ++d;
   }
-  // mid levels: the first kMidBlocks workgroups, the others leave
-  if (shrink && blockIdx.x < (unsigned)kMidBlocks) {
+  // mid levels: the first lp.mid_blocks workgroups, the others leave
+  if (shrink && blockIdx.x < (unsigned)lp.mid_blocks) {
     if (!agg_clean) agg_reset(L), agg_clean = true;
     const int64_t mtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t mthreads = (int64_t)kMidBlocks * blockDim.x;
-    while (lo < hi && hi - lo >= kTailRules) {
-      level_round(g, pend, level_cnt, L, lo, hi, d, mtid, mthreads, tokens);
-      group_barrier(bar, kMidBlocks, gen);
+    const int64_t mthreads = (int64_t)lp.mid_blocks * blockDim.x;
+    while (lo < hi && hi - lo >= lp.tail_rules) {
+      level_round(g, lp, status, level_cnt, L, lo, hi, d, mtid, mthreads, tokens);
+      group_barrier(bar, (uint32_t)lp.mid_blocks, gen);
       const int32_t next = __hip_atomic_load(&level_cnt[d + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (mtid == 0) {
         g.level_off[d] = lo;
@@ -459,7 +471,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
     while (lo < hi) {
       // one workgroup: the block barriers inside the round order its global
       // writes (level list, weights, pending counts) for the next round
-      level_round(g, pend, level_cnt, L, lo, hi, d, threadIdx.x, blockDim.x, tokens);
+      level_round(g, lp, status, level_cnt, L, lo, hi, d, threadIdx.x, blockDim.x, tokens);
       __syncthreads();
       const int32_t next = L.list_total;
       if (threadIdx.x == 0) {
@@ -487,16 +499,15 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   }
 }
 
-hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
-                                 hipStream_t s) {
+hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s) {
   // level 1 by compaction (scratch: per-block counts, then the scan's block sums)
   const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
-  k_zero_count<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch);
+  k_zero_count<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = launch_scan_u32(scratch, nb, &lc->frontier0, scratch + nb, s);
   if (e != hipSuccess) return e;
-  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(pend, g.R, scratch, g.level_rule);
+  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch, g.level_rule);
   return hipGetLastError();
 }
 
@@ -504,14 +515,15 @@ hipError_t launch_level_frontier(const DevGrammar& g, int32_t* pend, LoadCounter
 // rules (bucket = id mod nbk). Each block sums a range of kCapRules rules
 // into an LDS table by bucket, then adds it to the (zeroed) capacities.
 constexpr int kCapRules = 65536;
-__global__ __launch_bounds__(1024) void k_wide_caps(const int32_t* pend, int64_t R, uint32_t* cap, int nbk) {
+__global__ __launch_bounds__(1024) void k_wide_caps(const uint64_t* pw, int64_t R, uint32_t* cap, int nbk) {
   __shared__ uint32_t h[kWideMaxBuckets];
   for (int k = threadIdx.x; k < nbk; k += blockDim.x) h[k] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kCapRules;
   for (int k = threadIdx.x; k < kCapRules; k += blockDim.x) {
     const int64_t c = base + k;
-    if (c < R && pend[c]) atomicAdd(&h[c & (nbk - 1)], (uint32_t)pend[c]);
+    const uint32_t p = c < R ? (uint32_t)(pw[c] & kPendMask) : 0u;
+    if (p) atomicAdd(&h[c & (nbk - 1)], p);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < nbk; k += blockDim.x)
@@ -524,14 +536,14 @@ static uint32_t* level_barrier_words(const DevGrammar& g, uint32_t* scratch) {
   return scratch + nb + scan_sums_entries(nb);
 }
 
-hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* lc, uint32_t* scratch,
-                              const WideBufs& wide, hipStream_t s) {
+hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, const WideBufs& wide,
+                              hipStream_t s) {
   const WideBufs& wb = wide;
   if (wb.ew) {
     // bucket regions: exclusive scan of the capacities; both cursors start there
     hipError_t e0 = launch_fill_i32(reinterpret_cast<int32_t*>(wb.cur), wb.nbk, 0, s);
     if (e0 != hipSuccess) return e0;
-    k_wide_caps<<<(unsigned)((g.R + kCapRules - 1) / kCapRules), 1024, 0, s>>>(pend, g.R, wb.cur, wb.nbk);
+    k_wide_caps<<<(unsigned)((g.R + kCapRules - 1) / kCapRules), 1024, 0, s>>>(g.w, g.R, wb.cur, wb.nbk);
     e0 = hipGetLastError();
     if (e0 == hipSuccess) e0 = launch_scan_u32(wb.cur, wb.nbk, &lc->wide_entries, scratch, s);
     if (e0 == hipSuccess)
@@ -541,8 +553,8 @@ hipError_t prepare_level_walk(const DevGrammar& g, int32_t* pend, LoadCounters* 
   return launch_fill_i32(reinterpret_cast<int32_t*>(level_barrier_words(g, scratch)), 2, 0, s);
 }
 
-hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_cnt, LoadCounters* lc,
-                             uint32_t* scratch, const WideBufs& wide, int device, hipStream_t s) {
+hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
+                             const WideBufs& wide, const LevelParams& params, int device, hipStream_t s) {
   WideBufs wb = wide;
   int per_cu = 0, cus = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_levels), kLevelThreads, 0);
@@ -555,7 +567,10 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* pend, int32_t* level_
   const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
   DevGrammar gg = g;
   uint32_t* bar = level_barrier_words(g, scratch);
-  void* args[] = {&gg, &pend, &level_cnt, &lc, &wb, &bar};
+  LevelParams lp = params;
+  if (lp.mid_blocks < 1) lp.mid_blocks = 1;
+  if (lp.tail_rules < 1) lp.tail_rules = 1;
+  void* args[] = {&gg, &level_cnt, &lc, &wb, &lp, &bar};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_levels), dim3(grid), dim3(kLevelThreads), args, 0,
                                     s);
 }

@@ -113,7 +113,7 @@ __device__ __forceinline__ void load4(const DevGrammar& g, const Tile& t, int32_
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, int32_t* pend, LoadCounters* lc) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, LoadCounters* lc) {
   extern __shared__ int32_t lds_scan[];
   int32_t* roff = lds_scan;
   uint32_t* whist = reinterpret_cast<uint32_t*>(lds_scan + kTileRuleSlots);
@@ -151,8 +151,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, int
           const int64_t c = -(int64_t)s;
           if (c >= g.R) bad |= ST_BAD_REF;
           else if (rnb) atomicAdd(&rhist[c >> kRcBits], 1u);
-          else if (r == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), 1ull);
-          else atomicAdd(&pend[c], 1);
+          else if (r == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), 1ull << kPendBits);
+          else if ((atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), 1ull) & kPendMask) == kPendMask)
+            bad |= ST_PACK;
         }
       }
     }
@@ -176,10 +177,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, int
   if (bad) atomicOr(&lc->status, bad);
 }
 
-hipError_t launch_scan_symbols(const DevGrammar& g, int32_t* pend, LoadCounters* lc, hipStream_t s) {
+hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_t s) {
   if (g.ntiles == 0) return hipSuccess;
   const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.wc_nb + g.rc_nb);
-  k_scan_symbols<<<(unsigned)g.nblk, kScanThreads, shmem, s>>>(g, pend, lc);
+  k_scan_symbols<<<(unsigned)g.nblk, kScanThreads, shmem, s>>>(g, lc);
   return hipGetLastError();
 }
 
@@ -223,14 +224,15 @@ __global__ __launch_bounds__(kScanThreads) void k_ref_scatter(DevGrammar g, uint
 // very uneven: preorder numbering gives the most used rules small ids).
 // Occurrences in the root add to the initial weight (frequency in the root),
 // the others to the count of pending in-edges; per bucket segment both are
-// summed in LDS and added to the zeroed outputs with coalesced atomics. The
+// summed in LDS and added to the zeroed packed words with one coalesced
+// atomic per rule (a field overflow sets ST_PACK). The
 // most common key of each wave step is merged with one ballot first (every
 // entry counts 1), which takes the bulk of the same-address LDS updates.
 constexpr int kRcThreads = 1024;
 constexpr int64_t kRcChunk = 32 * kRcThreads;
 
 __global__ __launch_bounds__(kRcThreads) void k_ref_reduce(DevGrammar g, const uint16_t* entries, const int64_t* total,
-                                                           int32_t* pend) {
+                                                           LoadCounters* lc) {
   __shared__ uint32_t in_root[kRcBucket];
   __shared__ uint32_t in_rules[kRcBucket];
   __shared__ int first_bucket;
@@ -271,18 +273,19 @@ __global__ __launch_bounds__(kRcThreads) void k_ref_reduce(DevGrammar g, const u
       const int64_t c = base + i;
       const uint32_t r = in_root[i], p = in_rules[i];
       in_root[i] = 0, in_rules[i] = 0;
-      if (c >= g.R) continue;
-      if (r) atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]), (unsigned long long)r);
-      if (p) atomicAdd(&pend[c], (int32_t)p);
+      if (c >= g.R || (r | p) == 0) continue;
+      const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&g.w[c]),
+                                     ((unsigned long long)r << kPendBits) + p);
+      if ((old & kPendMask) + p > kPendMask || (old >> kPendBits) + r >= (1ull << kWeightBits))
+        atomicOr(&lc->status, (uint32_t)ST_PACK);
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entries, const int64_t* n, hipStream_t s) {
+hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s) {
   if (g.rc_nb == 0) return hipSuccess;  // counted with direct atomics by the scan
   hipError_t e0 = launch_fill_u64(g.w, g.R, 0, s);
-  if (e0 == hipSuccess) e0 = launch_fill_i32(pend, g.R, 0, s);
   if (e0 != hipSuccess) return e0;
   if (g.ntiles > 0) {
     const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.rc_nb);
@@ -293,11 +296,25 @@ hipError_t launch_in_degrees(const DevGrammar& g, int32_t* pend, uint16_t* entri
   // at most S entries; chunks past the actual count exit at once
   const int64_t chunks = (g.S + kRcChunk - 1) / kRcChunk;
   if (chunks > 0) {
-    k_ref_reduce<<<(unsigned)chunks, kRcThreads, 0, s>>>(g, entries, n, pend);
+    k_ref_reduce<<<(unsigned)chunks, kRcThreads, 0, s>>>(g, entries, n, lc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  k_fill_u64<<<1, 64, 0, s>>>(g.w, 1, 1);  // the root's weight
+  k_fill_u64<<<1, 64, 0, s>>>(g.w, 1, 1);  // the root's weight (never packed: the root has no in-edges)
+  return hipGetLastError();
+}
+
+// Unpacking after the level walk: every placed rule's pending field is zero,
+// so its weight is the word shifted down (the root keeps its weight 1).
+__global__ __launch_bounds__(256) void k_unpack_weights(uint64_t* w, int64_t R) {
+  for (int64_t r = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x)
+    w[r] >>= kPendBits;
+}
+
+hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s) {
+  if (g.R <= 1) return hipSuccess;
+  const int64_t want = (g.R + 255) / 256;
+  k_unpack_weights<<<(unsigned)(want < 8192 ? want : 8192), 256, 0, s>>>(g.w, g.R);
   return hipGetLastError();
 }
 

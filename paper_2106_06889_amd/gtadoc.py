@@ -67,6 +67,7 @@ EXPORTS = {
     "gtadoc_ranked_inverted_index": [_vp, _vp, _vp],
     "gtadoc_ranked_inverted_index_from_tv": [_vp, _vp, _vp, _vp],
     "gtadoc_sequence_count": [_vp, _int, _vp, _vp],
+    "gtadoc_sequence_count_wide": [_vp, _int, _vp, _vp],
     "gtadoc_result_array": [_vp, _int, _vp, _vp, _vp],
     "gtadoc_result_free": [_vp],
     "gtadoc_ctx_set_param": [_vp, _int, _i64],
@@ -79,6 +80,7 @@ EXPORTS = {
     "gtadoc_last_error": [],
 }
 PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING, PARAM_LEVEL_WIDE = 1, 2, 3, 4, 5
+PARAM_LEVEL_LONG_BODY, PARAM_LEVEL_MID_RULES, PARAM_LEVEL_MID_BLOCKS, PARAM_LEVEL_TAIL_RULES = 6, 7, 8, 9
 PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6,
           "decompress": 7, "tv_topdown": 8}
 TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN = 0, 1, 2
@@ -328,6 +330,11 @@ class Grammar:
     def ranked_inverted_index_from(self, term_vector: "Result", stream=None) -> Result:
         """The ranked inverted index from a term vector result of this grammar."""
         return self._result(lib().gtadoc_ranked_inverted_index_from_tv, term_vector.handle, stream=stream)
+
+    def sequence_count_wide(self, n: int, stream=None) -> Result:
+        """n-gram counts (n in 2..8) with 126-bit keys: arrays (hi int64[U],
+        lo int64[U], count int64[U]), ascending (hi, lo)."""
+        return self._result(lib().gtadoc_sequence_count_wide, n, stream=stream)
 
     def sequence_count(self, n: int, stream=None) -> Result:
         return self._result(lib().gtadoc_sequence_count, n, stream=stream)

@@ -211,12 +211,31 @@ def compress(tokens: np.ndarray, file_off: np.ndarray, vocab: int) -> Grammar:
 
 
 def workload(name: str, scale: float = 1.0) -> tuple[Corpus, Grammar]:
-    """Corpus and grammar of a named workload, optionally scaled down."""
+    """Corpus and grammar of a named workload, optionally scaled down. With
+    GTADOC_SYNTH_CACHE set to a directory, the pair is kept there (.npz,
+    keyed by the recipe) and reused by later calls."""
     spec = WORKLOADS[name]
     if scale != 1.0:
         spec = spec.scaled(scale)
+    cache = os.environ.get("GTADOC_SYNTH_CACHE")
+    path = None
+    if cache:
+        import hashlib
+        key = hashlib.sha256(repr(spec).encode()).hexdigest()[:16]
+        path = os.path.join(cache, f"{name.replace('/', '_')}-{key}.npz")
+        if os.path.exists(path):
+            z = np.load(path)
+            return (Corpus(z["tokens"], z["file_off"], int(z["vocab"])),
+                    Grammar(z["rule_off"], z["sym"], z["g_file_off"], int(z["vocab"])))
     c = corpus(spec)
-    return c, compress(c.tokens, c.file_off, c.vocab)
+    g = compress(c.tokens, c.file_off, c.vocab)
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, tokens=c.tokens, file_off=c.file_off, vocab=c.vocab, rule_off=g.rule_off, sym=g.sym,
+                 g_file_off=g.file_off)
+        os.replace(tmp, path)
+    return c, g
 
 
 def random_corpus(seed: int, files: int, max_tokens: int, vocab: int, run_bias: float = 0.3) -> Corpus:

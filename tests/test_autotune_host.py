@@ -65,3 +65,21 @@ def test_size_bucket():
     assert autotune.size_bucket(1024) == "2^10"
     assert autotune.size_bucket(1500) == "2^10"
     assert autotune.size_bucket(2 ** 27) == "2^27"
+
+
+def test_greedy_load_parameters(monkeypatch):
+    """The level walk's launch shape and the word-count chunk: a timing
+    function with a separable optimum inside the candidate lists is found
+    one parameter at a time, and the best values are left set."""
+    ctx = FakeCtx()
+    target = {gt.PARAM_LEVEL_WIDE: 524288, gt.PARAM_LEVEL_MID_RULES: 16384, gt.PARAM_LEVEL_MID_BLOCKS: 64,
+              gt.PARAM_LEVEL_TAIL_RULES: 4096, gt.PARAM_LEVEL_LONG_BODY: 64, gt.PARAM_WC_CHUNK: 8192}
+
+    def fake_time(fn, reps):
+        fn()
+        return sum(abs(ctx.params[p] - v) / v for p, v in target.items())
+    monkeypatch.setattr(autotune, "_time", fake_time)
+    res = autotune.greedy(ctx, autotune.LOAD_CANDIDATES, autotune.LOAD_DEFAULTS, lambda: None, reps=1)
+    for p, v in target.items():
+        assert ctx.params[p] == v
+        assert res["params"][autotune.NAMES[p]] == v

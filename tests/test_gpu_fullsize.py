@@ -134,3 +134,22 @@ def test_seq4_20m_full(ctx):
     wk, wc = oracle.traverse_sequence_count(g, 4)
     assert np.array_equal(k, wk) and np.array_equal(cnt, wc)
     assert int(cnt.sum()) == T - 3
+
+
+@pytest.mark.timeout(600)
+def test_seq_20m_fourgrams_wide_full(ctx):
+    """4-gram counts of the 20M-token nested-repeat corpus with its own
+    vocabulary of 200,000 words (too large for 16-bit key fields), through
+    the wide keys, against the oracle's traversal."""
+    import paper_2106_06889_amd as gt
+    c, g = synth.workload("seq-20m")
+    T = len(c.tokens)
+    del c
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    res = G.sequence_count_wide(4)
+    got = tuple(gt.to_u64(a) for a in res.arrays)
+    res.free()
+    G.free()
+    want = oracle.traverse_sequence_count_wide(g, 4)
+    assert all(np.array_equal(a, b) for a, b in zip(got, want))
+    assert int(got[2].sum()) == T - 3

@@ -146,3 +146,72 @@ def gpu_sc_of(ctx, g, n):
         return gpu_sc(G, n)
     finally:
         G.free()
+
+
+def gpu_wide(G, n):
+    import paper_2106_06889_amd as gt
+    res = G.sequence_count_wide(n)
+    out = tuple(gt.to_u64(a) for a in res.arrays)
+    res.free()
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_wide_keys_random_corpora(ctx, seed):
+    """Wide keys for every n in 2..8 (as far as n * bits(V - 1) <= 126),
+    bit-exact against the oracle's traversal and its brute force."""
+    c = synth.random_corpus(700 + seed, 1 + seed % 4, 2500, [3, 40, 900, 70000, 5, 200][seed])
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        for n in range(2, 9):
+            if n * oracle.wide_bits(c.vocab) > 126:
+                continue
+            got = gpu_wide(G, n)
+            want = oracle.traverse_sequence_count_wide(g, n)
+            assert all(np.array_equal(a, b) for a, b in zip(got, want)), n
+            brute = oracle.sc_text_wide(c.tokens, c.file_off, n, c.vocab)
+            assert all(np.array_equal(a, b) for a, b in zip(got, brute)), n
+    finally:
+        G.free()
+
+
+def test_wide_keys_golden_fivegrams(ctx):
+    d = json.load(open(os.path.join(GOLD, "e1_fivegrams.json")))
+    tok = np.array(d["tokens"], np.int32)
+    g = synth.compress(tok, np.array(d["file_off_text"], np.int64), d["vocab"])
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    hi, lo, cnt = gpu_wide(G, 5)
+    G.free()
+    assert oracle.unpack_wide(hi, lo, 5, d["vocab"]).tolist() == d["grams"]
+    assert cnt.tolist() == d["counts"]
+
+
+def test_wide_keys_errors(ctx):
+    import paper_2106_06889_amd as gt
+    c = synth.random_corpus(3, 2, 300, 1 << 30)
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        for n, code in ((1, gt.ERR_INVALID_ARG), (9, gt.ERR_INVALID_ARG), (5, gt.ERR_UNSUPPORTED)):
+            with pytest.raises(gt.GtadocError) as e:
+                G.sequence_count_wide(n)
+            assert e.value.code == code, n
+    finally:
+        G.free()
+
+
+@pytest.mark.timeout(300)
+def test_wide_keys_seq_recipe(ctx):
+    """The nested-repeat recipe (V = 200,000, so 4-grams do not fit 64-bit
+    keys) at n = 4 and n = 7, scaled to 1/20."""
+    c, g = synth.workload("seq-20m", scale=0.05)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    try:
+        for n in (4, 7):
+            got = gpu_wide(G, n)
+            want = oracle.traverse_sequence_count_wide(g, n)
+            assert all(np.array_equal(a, b) for a, b in zip(got, want)), n
+            assert int(got[2].sum()) == len(c.tokens) - n + 1
+    finally:
+        G.free()
