@@ -33,11 +33,11 @@ METRIC = {"wc": "uncompressed words/s analysed (word count)",
           "sc4": "uncompressed words/s analysed (sequence count, n = 4)",
           "tv": "uncompressed words/s analysed (term vector + inverted index)",
           "rii": "uncompressed words/s analysed (term vector + ranked inverted index)"}
-STEP = {"wc": "load (validate, levels, weights) + word count + sort",
-        "sc": "load + sequence count n=2 + sequence count n=3",
-        "sc4": "load + sequence count n=4",
-        "tv": "load + term vector + inverted index",
-        "rii": "load + term vector + ranked inverted index"}
+STEP = {"wc": "load (validate, in-degrees, weights by the dataflow walk) + word count + sort",
+        "sc": "load (validate, in-degrees, levels and weights) + sequence count n=2 + sequence count n=3",
+        "sc4": "load (validate, in-degrees, levels and weights) + sequence count n=4",
+        "tv": "load (validate, in-degrees, levels and weights) + term vector + inverted index",
+        "rii": "load (validate, in-degrees, levels and weights) + term vector + ranked inverted index"}
 
 
 def log(msg: str):
@@ -143,17 +143,13 @@ def cpu_baseline(query: str, g, file_tokens, budget_s: float) -> dict:
             "variants": variants, "host": host_info()}
 
 
-PHASE_KERNEL = {"levels": "k_levels"}
-
-
-def measured_traffic(phase: str, workload: str):
-    """HBM bytes per launch of the phase's kernel from a committed PMC
-    summary (profiles/*_hbm_traffic.md), or None when there is none for this
+def measured_traffic(kernel: str | None, workload: str):
+    """HBM bytes per launch of a kernel from a committed PMC summary
+    (profiles/*_hbm_traffic.md), or None when there is none for this
     workload or the kernel's source has changed since the counters were
     taken."""
     import glob
     import hashlib
-    kernel = PHASE_KERNEL.get(phase)
     if not kernel:
         return None
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
@@ -228,8 +224,12 @@ def run_query(args):
     sp = stream.cuda_stream
     sizes = {}
 
+    # the word count needs weights only; the other queries also need the
+    # levels, which the load then builds with the level walk
+    levels = q != "wc"
+
     def step():
-        G = ctx.load(ro, sym, fo, V, borrow=True)
+        G = ctx.load(ro, sym, fo, V, borrow=True, levels=levels)
         if q == "wc":
             gt.gtadoc._check(lib.gtadoc_word_count(G.handle, counts.data_ptr(), sp))
             gt.gtadoc._check(lib.gtadoc_sort(G.handle, counts.data_ptr(), ids.data_ptr(), scnt.data_ptr(),
@@ -252,17 +252,17 @@ def run_query(args):
     # this GPU and size, else a greedy search (the paper's parameter
     # selection) on this grammar before anything is timed
     from paper_2106_06889_amd import autotune
-    tune_key = f"{autotune.arch()}/load/{autotune.size_bucket(T)}"
+    tune_key = f"{autotune.arch()}/{'load-levels' if levels else 'load-flow'}/{autotune.size_bucket(T)}"
     tuned = "defaults"
     if not args.no_tune:
         if autotune.apply(ctx, tune_key):
             tuned = "cache"
         else:
-            res = autotune.tune_load(ctx, ro, sym, fo, V, reps=3)
+            res = autotune.tune_load(ctx, ro, sym, fo, V, reps=3, levels=levels)
             autotune.save(tune_key, res)
             tuned = "searched on this grammar before the timed region"
     tuned_params = {name: ctx.get_param(p) for p, name in autotune.NAMES.items()
-                    if p in autotune.LOAD_CANDIDATES}
+                    if p in (autotune.LOAD_CANDIDATES if levels else autotune.FLOW_CANDIDATES)}
     log(f"load parameters ({tuned}): {tuned_params}")
 
     for i in range(args.warmup):
@@ -271,7 +271,8 @@ def run_query(args):
     torch.cuda.synchronize()
 
     # sanity: exact totals against the grammar's own token count
-    G = ctx.load(ro, sym, fo, V, borrow=True)
+    G = ctx.load(ro, sym, fo, V, borrow=True, levels=levels)
+    G.build_levels()  # the depth, for the record (built here when the load did not)
     st = G.stats
     if q == "wc":
         total = int(gt.to_u64(G.word_count()).sum())
@@ -374,9 +375,12 @@ def run_query(args):
     #   word count  : all bodies, rule offsets, weights, counts written
     #   seq windows : all bodies, rule offsets, weights, len, head+tail, the distinct (key, count) pairs
     #   tv tables   : non-root bodies, rule offsets, the per-rule tables written (8 B per entry)
+    #   dataflow walk: non-root bodies, rule offsets, weights written
     wc_bytes = 4 * S + 8 * (R + 1) + 8 * R + 8 * V
     lv_bytes = 4 * (S - root_syms) + 8 * (R + 1) + 8 * R + 4 * R
-    cands = {"levels": ("level walk (k_levels)", lv_bytes),
+    flow_bytes = 4 * (S - root_syms) + 8 * (R + 1) + 8 * R
+    walk_kernel = "k_levels" if levels else "k_flow"
+    cands = {"levels": ("level walk (k_levels)", lv_bytes) if levels else ("dataflow walk (k_flow)", flow_bytes),
              "word_count": ("word count pass (bucket scatter + reduce)", wc_bytes)}
     if q in SEQ_NS:
         ns = SEQ_NS[q]
@@ -394,7 +398,7 @@ def run_query(args):
     dom = max((p for p in cands if p in phases), key=lambda p: phases[p]["avg_us"] * phases[p]["count"])
     roof = roofline(cands[dom][0], cands[dom][1], phases[dom]["avg_us"])
     if args.scale == 1.0:
-        roof["traffic"] = measured_traffic(dom, args.workload)
+        roof["traffic"] = measured_traffic(walk_kernel if dom == "levels" else None, args.workload)
     others = {p: roofline(cands[p][0], cands[p][1], phases[p]["avg_us"]) for p in cands if p in phases and p != dom}
     # the same kernels in the cold steps (grammar read from HBM, not the Infinity Cache)
     roof_cold = {p: roofline(cands[p][0], cands[p][1], phases_cold[p]["avg_us"]) for p in cands if p in phases_cold}
@@ -516,24 +520,26 @@ def run_compare(args):
         kinds = ["tv"] if F > 1 else ["wc", "sc2"]
         rows = {}
         for kind in kinds:
-            # compressed: load (levels, weights) + query from the resident grammar
+            lv = kind != "wc"  # the term vector and the n-gram count also need the levels
+
+            # compressed: load (weights, levels when needed) + query from the resident grammar
             def comp():
-                G = ctx.load(ro, sym, fo, V, borrow=True)
+                G = ctx.load(ro, sym, fo, V, borrow=True, levels=lv)
                 query(G, kind)
                 G.free()
 
             # uncompressed, resident text: the same query kernels on a one-rule grammar of the tokens
             def plain():
-                P = ctx.load(text_ro, text, text_off, V, borrow=True)
+                P = ctx.load(text_ro, text, text_off, V, borrow=True, levels=lv)
                 query(P, kind)
                 P.free()
 
             # decompression on the GPU, then the analytics on the text
-            Gd = ctx.load(ro, sym, fo, V, borrow=True)
+            Gd = ctx.load(ro, sym, fo, V, borrow=True, levels=True)
 
             def dec_plain():
                 tok, off = Gd.decompress()
-                P = ctx.load(text_ro, tok, off, V, borrow=True)
+                P = ctx.load(text_ro, tok, off, V, borrow=True, levels=lv)
                 query(P, kind)
                 P.free()
             r = {"compressed_ms": device_times(stream, comp, reps),
@@ -555,7 +561,7 @@ def run_compare(args):
                     "step": "compressed: load + query; uncompressed: load of the one-rule text grammar + the same "
                             "query; decompress: GPU decompression + that"})
     else:
-        Gs = ctx.load(ro, sym, fo, V, borrow=True)
+        Gs = ctx.load(ro, sym, fo, V, borrow=True, levels=True)
         choice = {gt.TV_TOP_DOWN: "top-down", gt.TV_BOTTOM_UP: "bottom-up"}[Gs.tv_strategy()]
         rows = {}
         for name, strat in (("bottom-up", gt.TV_BOTTOM_UP), ("top-down", gt.TV_TOP_DOWN)):

@@ -67,6 +67,10 @@ extern "C" {
                                   reference instead of copying; they must stay alive
                                   and unchanged until gtadoc_free_grammar, and sym
                                   must be 16-byte aligned */
+#define GTADOC_LOAD_LEVELS 0x8u /* build the level structure during the load (one
+                                  level-synchronous walk gives levels and weights);
+                                  without it the load computes the weights with the
+                                  dataflow walk and the levels are built on first need */
 
 typedef struct gtadoc_ctx_s* gtadoc_ctx;
 typedef struct gtadoc_grammar_s* gtadoc_grammar;
@@ -80,7 +84,9 @@ typedef struct {
   int64_t files;       /* F */
   int64_t word_syms;   /* W: word symbols in all bodies */
   int64_t root_syms;   /* symbols in the root body */
-  int64_t depth;       /* D: number of rule levels below the root (longest path) */
+  int64_t depth;       /* D: number of rule levels below the root (longest path);
+                          -1 until the levels are built (GTADOC_LOAD_LEVELS,
+                          gtadoc_build_levels, or a query that needs them) */
   int32_t vocab;       /* V */
   int32_t reserved;
   uint64_t arena_bytes; /* arena bytes the grammar holds */
@@ -106,12 +112,16 @@ int gtadoc_ctx_usage(gtadoc_ctx ctx, uint64_t* in_use, uint64_t* peak, uint64_t*
 /* Load a compressed text (encoding above) into the context and prepare it
  * for queries: validation, then the initialization phase of the paper
  * (Section "Overview", phases; Algorithm "Top-Down Traversal", mask
- * initialization and traversal): in-degrees of the rules, the level-by-level
- * topological frontiers of the rule DAG, and the top-down rule weights
- * (weight(root) = 1, weight(c) = sum over the occurrences of c in body(p) of
- * weight(p)). Blocks until the load has finished on `stream` (it reads back
- * the validation status and the level structure). Host inputs may be freed
- * on return; copied device inputs once the call has returned.
+ * initialization and traversal): in-degrees of the rules and the top-down
+ * rule weights (weight(root) = 1, weight(c) = sum over the occurrences of c
+ * in body(p) of weight(p)), and with GTADOC_LOAD_LEVELS the level-by-level
+ * topological frontiers of the rule DAG (level = longest path from the
+ * root). Without the flag the weights come from a dataflow walk (a rule is
+ * walked as soon as its last in-edge arrives, no level barriers), and the
+ * levels, which the word count and sort do not use, are built by the first
+ * call that needs them. Blocks until the load has finished on `stream` (it
+ * reads back the validation status). Host inputs may be freed on return;
+ * copied device inputs once the call has returned.
  * Errors: INVALID_ARG, BAD_GRAMMAR, CYCLE, OOM, HIP; UNSUPPORTED when a rule
  * occurs 2^40 or more times in the text or is referenced 2^24 or more times
  * by other rules (the load keeps a rule's weight and pending in-edges in one
@@ -121,6 +131,14 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t num_rul
                         uint32_t flags, void* stream, gtadoc_grammar* out);
 
 int gtadoc_grammar_stats(gtadoc_grammar g, gtadoc_stats* out);
+
+/* Build the level structure of a grammar loaded without GTADOC_LOAD_LEVELS
+ * (Algorithm "Top-Down Traversal", the rounds as levels): the in-degree pass
+ * again into scratch, then the level walk; afterwards the stats carry the
+ * depth. Does nothing when the levels exist. Term vectors, inverted indexes,
+ * sequence counts, decompression, query footprints and mixed batches call
+ * it themselves. Synchronizes `stream`. Errors: INVALID_ARG, OOM, HIP. */
+int gtadoc_build_levels(gtadoc_grammar g, void* stream);
 
 /* E: the number of distinct (parent, child) rule pairs of the DAG (root
  * included), counted on the first call and kept. Synchronizes `stream` on
@@ -269,6 +287,9 @@ int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void
 #define GTADOC_PARAM_LEVEL_MID_RULES 7  /* load: levels narrower than this run on MID_BLOCKS workgroups */
 #define GTADOC_PARAM_LEVEL_MID_BLOCKS 8 /* load: workgroups of the narrower levels (1..256); default 32 */
 #define GTADOC_PARAM_LEVEL_TAIL_RULES 9 /* load: levels narrower than this run on one workgroup; default 1024 */
+#define GTADOC_PARAM_FLOW_KEEP 10       /* load, dataflow walk: ready rules a workgroup keeps in its ring at
+                                          the end of a round; the rest go to the shared queue (0..7168;
+                                          default 4096) */
 
 /* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);
@@ -279,7 +300,8 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value);
  * around each of the phases below; gtadoc_ctx_phase_time waits for the
  * recorded events and returns the summed device time (ms) and the number of
  * timed occurrences, optionally resetting them. */
-#define GTADOC_PHASE_LEVELS 0       /* load: the level walk (frontiers and top-down weights), one kernel */
+#define GTADOC_PHASE_LEVELS 0       /* load: the weight walk (the level walk or the dataflow walk), one
+                                       kernel; also the level walk of gtadoc_build_levels */
 #define GTADOC_PHASE_WORD_COUNT 1   /* word count: bucket scatter + on-chip reduce */
 #define GTADOC_PHASE_SORT 2         /* sort: compaction + radix passes */
 #define GTADOC_PHASE_SEQ_WINDOWS 3  /* sequence count: owned windows into the exact hash table, one kernel */
@@ -337,8 +359,10 @@ typedef struct {
  * streams (four, default priority; sequence counts of one grammar share a
  * stream), all of them ordered after the context's earlier work, so their
  * kernels overlap on the device with each other and with the word counts.
- * The call returns once every query is queued (variable-size results
- * synchronize their own stream for their sizes); all of the batch's work is
+ * Grammars loaded without levels get them first (gtadoc_build_levels, once
+ * per grammar, synchronizing `stream`) when a query other than a word count
+ * needs them. The call returns once every query is queued (variable-size
+ * results synchronize their own stream for their sizes); all of the batch's work is
  * complete when `stream` passes the point of return. Each query's status is
  * written to q[i].status (OOM, UNSUPPORTED, ... for that query alone).
  * Errors of the call itself: INVALID_ARG (a malformed query: null or foreign

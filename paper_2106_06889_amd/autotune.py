@@ -36,7 +36,7 @@ DEFAULTS = {gt.PARAM_BATCH_BLOCKS_PER_CU: 4, gt.PARAM_WC_CHUNK: 32768}
 NAMES = {gt.PARAM_BATCH_BLOCKS_PER_CU: "batch_blocks_per_cu", gt.PARAM_WC_CHUNK: "wc_chunk",
          gt.PARAM_LEVEL_WIDE: "level_wide", gt.PARAM_LEVEL_LONG_BODY: "level_long_body",
          gt.PARAM_LEVEL_MID_RULES: "level_mid_rules", gt.PARAM_LEVEL_MID_BLOCKS: "level_mid_blocks",
-         gt.PARAM_LEVEL_TAIL_RULES: "level_tail_rules"}
+         gt.PARAM_LEVEL_TAIL_RULES: "level_tail_rules", gt.PARAM_FLOW_KEEP: "flow_keep"}
 
 # the load (level walk) and the single-grammar word count, in search order
 LOAD_CANDIDATES = {
@@ -49,6 +49,13 @@ LOAD_CANDIDATES = {
 }
 LOAD_DEFAULTS = {gt.PARAM_LEVEL_WIDE: 262144, gt.PARAM_LEVEL_MID_RULES: 49152, gt.PARAM_LEVEL_MID_BLOCKS: 32,
                  gt.PARAM_LEVEL_TAIL_RULES: 1024, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 32768}
+# the load by the dataflow walk (no levels) and the word count
+FLOW_CANDIDATES = {
+    gt.PARAM_FLOW_KEEP: [512, 2048, 4096, 7168],
+    gt.PARAM_LEVEL_LONG_BODY: [16, 32, 64, 128],
+    gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
+}
+FLOW_DEFAULTS = {gt.PARAM_FLOW_KEEP: 4096, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 32768}
 
 
 def arch() -> str:
@@ -117,17 +124,21 @@ def greedy(ctx, candidates: dict, defaults: dict, run, reps: int, verbose: bool 
     return {"params": {NAMES[p]: v for p, v in best.items()}, "timings_ms": timings}
 
 
-def tune_load(ctx: gt.Context, rule_off, sym, file_off, vocab: int, reps: int = 3, verbose: bool = False) -> dict:
-    """Greedy search of the level walk's launch shape and the word-count
-    chunk on a sample grammar (device tensors, loaded by borrowing): each
-    candidate is timed over a load followed by a word count."""
+def tune_load(ctx: gt.Context, rule_off, sym, file_off, vocab: int, reps: int = 3, verbose: bool = False,
+              levels: bool = False) -> dict:
+    """Greedy search of the weight walk's launch shape (the level walk with
+    levels=True, else the dataflow walk) and the word-count chunk on a sample
+    grammar (device tensors, loaded by borrowing): each candidate is timed
+    over a load followed by a word count."""
     out = torch.empty(vocab, dtype=torch.int64, device=ctx.device)
 
     def run():
-        G = ctx.load(rule_off, sym, file_off, vocab, borrow=True)
+        G = ctx.load(rule_off, sym, file_off, vocab, borrow=True, levels=levels)
         G.word_count(out)
         G.free()
-    return greedy(ctx, LOAD_CANDIDATES, LOAD_DEFAULTS, run, reps, verbose)
+    if levels:
+        return greedy(ctx, LOAD_CANDIDATES, LOAD_DEFAULTS, run, reps, verbose)
+    return greedy(ctx, FLOW_CANDIDATES, FLOW_DEFAULTS, run, reps, verbose)
 
 
 def load_cache() -> dict:

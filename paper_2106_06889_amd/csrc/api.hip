@@ -182,6 +182,7 @@ struct gtadoc_grammar_s {
   gt::DevGrammar d{};
   gtadoc_stats st{};
   std::vector<int32_t> level_off;  // host copy, level_off[d] for d = 1..D+1
+  bool has_levels = false;         // level_rule / level_off / depth built (by the load or on first need)
   // head/tail/len buffers for sequences (first use of sequence count)
   uint64_t* seq_len = nullptr;
   int32_t* seq_head = nullptr;
@@ -388,6 +389,44 @@ int gtadoc_ctx_usage(gtadoc_ctx ctx, uint64_t* in_use, uint64_t* peak, uint64_t*
   return GTADOC_OK;
 }
 
+namespace {
+bool hip_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    fail(GTADOC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return false;
+  }
+  return true;
+}
+
+// The in-degree pass of the initialization phase on `s`: symbol ranges and
+// word totals (lc), the word-bucket offsets (d.wc_off), the reference-bucket
+// offsets (d.rc_off, scratch), then one packed word per rule in d.w
+// (frequency in the root << kPendBits | in-edges from other rules; the root
+// holds weight 1). Returns false with the error recorded.
+bool run_degrees(Call& call, gt::DevGrammar& d, gt::LoadCounters* lc, uint32_t* sums, int64_t n_wc_off,
+                 int64_t n_rc_off, hipStream_t s) {
+  const bool atomic_degrees = d.rc_nb == 0;
+  if ((atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, d.R, 0, s), "fill")) ||
+      (n_wc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
+      (n_rc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
+      !hip_ok(gt::launch_scan_symbols(d, lc, s), "scan_symbols") ||
+      (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
+      (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
+      (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, 1, 1, s), "fill")))
+    return false;
+  if (!atomic_degrees) {
+    // one entry per rule reference: at most S of them (the exact count stays on the device)
+    uint16_t* ref_entries = call.scratch<uint16_t>(d.S);
+    if (!ref_entries) {
+      oom("reference entries", 2 * (uint64_t)d.S);
+      return false;
+    }
+    if (!hip_ok(gt::launch_in_degrees(d, ref_entries, &lc->rc_entries, lc, s), "in_degrees")) return false;
+  }
+  return true;
+}
+}  // namespace
+
 int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, const int32_t* sym, int64_t S,
                         const int64_t* file_off, int64_t F, int32_t V, uint32_t flags, void* stream,
                         gtadoc_grammar* out) {
@@ -397,7 +436,10 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     return fail(GTADOC_ERR_INVALID_ARG, "bad sizes (R=%lld S=%lld F=%lld V=%d)", (long long)R, (long long)S,
                 (long long)F, V);
   const bool host = flags & GTADOC_IN_HOST, dev = flags & GTADOC_IN_DEVICE, borrow = flags & GTADOC_IN_BORROW;
-  if (host == dev || (borrow && !dev)) return fail(GTADOC_ERR_INVALID_ARG, "flags must be IN_HOST or IN_DEVICE[|BORROW]");
+  const bool want_levels = flags & GTADOC_LOAD_LEVELS;
+  if (host == dev || (borrow && !dev) ||
+      (flags & ~(GTADOC_IN_HOST | GTADOC_IN_DEVICE | GTADOC_IN_BORROW | GTADOC_LOAD_LEVELS)))
+    return fail(GTADOC_ERR_INVALID_ARG, "flags must be IN_HOST or IN_DEVICE[|BORROW], optionally LOAD_LEVELS");
   if (borrow && reinterpret_cast<uintptr_t>(sym) % 16 != 0)
     return fail(GTADOC_ERR_INVALID_ARG, "borrowed sym must be 16-byte aligned");
 
@@ -451,24 +493,29 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   const int64_t n_rc_off = (int64_t)d.rc_nb * d.nslot;
   d.wc_off = d.wc_nb ? call.keep<uint32_t>(n_wc_off, g->blocks) : nullptr;
   d.rc_off = d.rc_nb ? call.scratch<uint32_t>(n_rc_off) : nullptr;
-  int32_t* level_cnt = call.scratch<int32_t>(R + 2);
+  // the level walk's per-level counts, or the dataflow walk's queue weights,
+  // chunk descriptors and counters
+  int32_t* level_cnt = want_levels ? call.scratch<int32_t>(R + 2) : nullptr;
+  gt::FlowBufs flow{};
+  gt::FlowState* fs = nullptr;
+  if (!want_levels) {
+    flow.qc = d.level_rule;
+    flow.qw = call.scratch<uint64_t>(R);
+    flow.desc = call.scratch<uint64_t>(R);
+    flow.qcap = (uint32_t)std::max<int64_t>(R - 1, 1);
+    flow.ndesc = (uint32_t)R;
+    fs = call.scratch<gt::FlowState>(1);
+  }
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
   uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
                                                     nbR + gt::scan_scratch_entries(nbR) + 2}));
-  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !level_cnt || !lc || !sums ||
-      (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
+  if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !lc || !sums || (want_levels && !level_cnt) ||
+      (!want_levels && (!flow.qw || !flow.desc || !fs)) || (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return bail(oom("initialization-phase buffers", 28 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off)));
   d.tile_rule = tile_rule;
 
   auto* pc = reinterpret_cast<gt::LoadCounters*>(ctx->pinned);
-  auto hip_ok = [&](hipError_t e, const char* what) {
-    if (e != hipSuccess) {
-      fail(GTADOC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-      return false;
-    }
-    return true;
-  };
   // phase 1: offsets and file spans (must hold before any kernel indexes by them)
   if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
       !hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
@@ -489,7 +536,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     int32_t nbk_bits = 0;
     while (nbk * gt::kWideBucket < R) nbk <<= 1, ++nbk_bits;
     const int64_t nonroot = S - pc->root_syms;
-    if (ctx->level_wide > 0 && nbk <= gt::kWideMaxBuckets && nonroot > 0 && nonroot < (1ll << 32)) {
+    if (want_levels && ctx->level_wide > 0 && nbk <= gt::kWideMaxBuckets && nonroot > 0 && nonroot < (1ll << 32)) {
       wide.ew = call.scratch<uint64_t>(nonroot);
       wide.ec = call.scratch<uint16_t>(nonroot);
       wide.cur = call.scratch<uint32_t>(nbk);
@@ -501,41 +548,32 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
       if (!wide.ew || !wide.ec || !wide.cur || !wide.seg_lo) wide = gt::WideBufs{};
     }
   }
-  // phase 2: symbols, in-degrees, levels and weights
+  // phase 2: symbols, in-degrees, then the weight walk: the level walk
+  // (levels and weights) or the dataflow walk (weights; levels on first need)
   PhaseScope t_load(ctx, GTADOC_PHASE_LOAD, s);
-  const bool atomic_degrees = d.rc_nb == 0;
-  if (!hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill") ||
-      (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, R, 0, s), "fill")) ||
-      (n_wc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
-      (n_rc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
-      !hip_ok(gt::launch_scan_symbols(d, lc, s), "scan_symbols") ||
-      (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
-      (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
-      (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, 1, 1, s), "fill")))
+  if ((want_levels && !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill")) ||
+      (!want_levels && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(fs), sizeof(gt::FlowState) / 4, 0, s), "fill")))
     return bail(GTADOC_ERR_HIP);
-  if (!atomic_degrees) {
-    // one entry per rule reference: at most S of them (the exact count stays on the device)
-    uint16_t* ref_entries = call.scratch<uint16_t>(S);
-    if (!ref_entries) return bail(oom("reference entries", 2 * (uint64_t)S));
-    if (!hip_ok(gt::launch_in_degrees(d, ref_entries, &lc->rc_entries, lc, s), "in_degrees"))
-      return bail(GTADOC_ERR_HIP);
-  }
-  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s), "levels"))
+  if (!run_degrees(call, d, lc, sums, n_wc_off, n_rc_off, s)) return bail(GTADOC_ERR_HIP);
+  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s, want_levels ? nullptr : flow.qw), "levels"))
     return bail(GTADOC_ERR_HIP);
-  if (!hip_ok(gt::prepare_level_walk(d, lc, sums, wide, s), "levels"))
+  if (want_levels && !hip_ok(gt::prepare_level_walk(d, lc, sums, wide, s), "levels"))
     return bail(GTADOC_ERR_HIP);
-  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);  // the level walk kernel alone
-  if (!hip_ok(gt::launch_level_walk(d, level_cnt, lc, sums, wide, ctx->level, ctx->device, s), "levels"))
+  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);  // the walk kernel alone
+  if (!hip_ok(want_levels ? gt::launch_level_walk(d, level_cnt, lc, sums, wide, ctx->level, ctx->device, s)
+                          : gt::launch_flow_walk(d, lc, fs, flow, ctx->level, ctx->device, s),
+              "levels"))
     return bail(GTADOC_ERR_HIP);
   t_levels.end();
   if (!hip_ok(gt::launch_unpack_weights(d, s), "weights")) return bail(GTADOC_ERR_HIP);
   t_load.end();
-  // the counters and the first level offsets come back with one wait
+  // the counters (and the first level offsets) come back with one wait
   static_assert(sizeof(gt::LoadCounters) <= kPinnedLevelAt, "counters overlap the level offsets");
   int32_t* plevel = reinterpret_cast<int32_t*>(ctx->pinned + kPinnedLevelAt);
-  const int64_t nlev = std::min<int64_t>(R + 2, kPinnedLevels);
+  const int64_t nlev = want_levels ? std::min<int64_t>(R + 2, kPinnedLevels) : 0;
   if (!hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
-      !hip_ok(hipMemcpyAsync(plevel, d.level_off, sizeof(int32_t) * nlev, hipMemcpyDeviceToHost, s), "read levels") ||
+      (nlev && !hip_ok(hipMemcpyAsync(plevel, d.level_off, sizeof(int32_t) * nlev, hipMemcpyDeviceToHost, s),
+                       "read levels")) ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
   if (pc->status & (gt::ST_BAD_WORD | gt::ST_BAD_REF))
@@ -548,18 +586,23 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   if (d.wc_nb && pc->wc_entries != (int64_t)pc->word_syms)
     return bail(fail(GTADOC_ERR_HIP, "internal: word bucket histogram %lld != word symbols %llu",
                      (long long)pc->wc_entries, (unsigned long long)pc->word_syms));
+  if (pc->status & gt::ST_FLOW)
+    return bail(fail(GTADOC_ERR_HIP, "internal: the dataflow walk ran out of queue room or waited past its bound"));
   if (pc->placed != R - 1)
     return bail(fail(GTADOC_ERR_CYCLE, "rule graph has a cycle (%lld of %lld rules ordered)", (long long)pc->placed,
                      (long long)(R - 1)));
-  const int32_t D = pc->depth;
-  g->level_off.assign((size_t)D + 2, 0);
-  if (D > 0 && D + 2 <= nlev) {
-    std::copy(plevel, plevel + D + 2, g->level_off.begin());
-  } else if (D > 0) {
-    if (!hip_ok(hipMemcpyAsync(g->level_off.data(), d.level_off, sizeof(int32_t) * (D + 2), hipMemcpyDeviceToHost, s),
-                "read levels") ||
-        !hip_ok(hipStreamSynchronize(s), "sync"))
-      return bail(GTADOC_ERR_HIP);
+  const int32_t D = want_levels ? pc->depth : -1;
+  if (want_levels) {
+    g->level_off.assign((size_t)D + 2, 0);
+    if (D > 0 && D + 2 <= nlev) {
+      std::copy(plevel, plevel + D + 2, g->level_off.begin());
+    } else if (D > 0) {
+      if (!hip_ok(hipMemcpyAsync(g->level_off.data(), d.level_off, sizeof(int32_t) * (D + 2), hipMemcpyDeviceToHost, s),
+                  "read levels") ||
+          !hip_ok(hipStreamSynchronize(s), "sync"))
+        return bail(GTADOC_ERR_HIP);
+    }
+    g->has_levels = true;
   }
   gtadoc_stats& st = g->st;
   st.tokens = (int64_t)(pc->tokens + pc->root_words);
@@ -575,6 +618,68 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   st.arena_bytes = bytes;
   *out = g;
   return GTADOC_OK;
+}
+
+namespace {
+// Builds the level structure of a grammar loaded without it: the in-degree
+// pass again into scratch (the grammar's weights stay as they are), level 1,
+// then the level walk, which writes level_rule and level_off; the depth and
+// the level offsets come back to the host. Synchronizes the call's stream.
+int ensure_levels(gtadoc_grammar g, void* stream) {
+  if (g->has_levels) return GTADOC_OK;
+  gtadoc_ctx ctx = g->ctx;
+  Call call(ctx, stream);
+  int rc = call.begin();
+  if (rc) return rc;
+  hipStream_t s = call.stream();
+  gt::DevGrammar d = g->d;  // a copy whose packed words and histograms are scratch
+  const int64_t R = d.R;
+  const int64_t n_wc_off = (int64_t)d.wc_nb * d.nslot;
+  const int64_t n_rc_off = (int64_t)d.rc_nb * d.nslot;
+  d.w = call.scratch<uint64_t>(R);
+  d.wc_off = d.wc_nb ? call.scratch<uint32_t>(n_wc_off) : nullptr;
+  d.rc_off = d.rc_nb ? call.scratch<uint32_t>(n_rc_off) : nullptr;
+  int32_t* level_cnt = call.scratch<int32_t>(R + 2);
+  auto* lc = call.scratch<gt::LoadCounters>(1);
+  const int64_t nbR = (R + 4095) / 4096;
+  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
+                                                    nbR + gt::scan_scratch_entries(nbR) + 2}));
+  if (!d.w || !level_cnt || !lc || !sums || (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
+    return oom("level buffers", 16 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off));
+  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
+      !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill"))
+    return GTADOC_ERR_HIP;
+  if (!run_degrees(call, d, lc, sums, n_wc_off, n_rc_off, s)) return GTADOC_ERR_HIP;
+  const gt::WideBufs wide{};  // every level in the atomic mode
+  PhaseScope t_levels(ctx, GTADOC_PHASE_LEVELS, s);
+  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s), "levels") ||
+      !hip_ok(gt::prepare_level_walk(d, lc, sums, wide, s), "levels") ||
+      !hip_ok(gt::launch_level_walk(d, level_cnt, lc, sums, wide, ctx->level, ctx->device, s), "levels"))
+    return GTADOC_ERR_HIP;
+  t_levels.end();
+  gt::LoadCounters host{};
+  if (!hip_ok(hipMemcpyAsync(&host, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read counters") ||
+      !hip_ok(hipStreamSynchronize(s), "sync"))
+    return GTADOC_ERR_HIP;
+  if (host.status || host.placed != R - 1)  // the load has checked all of these
+    return fail(GTADOC_ERR_HIP, "internal: level walk status %u, %d of %lld rules placed", host.status, host.placed,
+                (long long)(R - 1));
+  const int32_t D = host.depth;
+  std::vector<int32_t> off((size_t)D + 2, 0);
+  if (D > 0 && (!hip_ok(hipMemcpyAsync(off.data(), d.level_off, sizeof(int32_t) * (D + 2), hipMemcpyDeviceToHost, s),
+                        "read levels") ||
+                !hip_ok(hipStreamSynchronize(s), "sync")))
+    return GTADOC_ERR_HIP;
+  g->level_off.swap(off);
+  g->st.depth = D;
+  g->has_levels = true;
+  return GTADOC_OK;
+}
+}  // namespace
+
+int gtadoc_build_levels(gtadoc_grammar g, void* stream) {
+  if (!g) return fail(GTADOC_ERR_INVALID_ARG, "null grammar");
+  return ensure_levels(g, stream);
 }
 
 int gtadoc_grammar_stats(gtadoc_grammar g, gtadoc_stats* out) {
@@ -653,6 +758,7 @@ int gtadoc_word_count_noalloc(gtadoc_grammar g, uint64_t* counts, void* stream) 
 
 int gtadoc_decompress(gtadoc_grammar g, int32_t* tokens, int64_t* file_off, void* stream) {
   if (!g || !file_off || (g->st.tokens > 0 && !tokens)) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (int rl = ensure_levels(g, stream)) return rl;
   const gt::DevGrammar& d = g->d;
   const int64_t T = g->st.tokens, R = d.R, nroot = g->st.root_syms;
   const int32_t D = (int32_t)g->st.depth;
@@ -979,6 +1085,7 @@ int term_vector_entry(gtadoc_grammar g, int strategy, gtadoc_result* out, void* 
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   if (strategy != GTADOC_TV_AUTO && strategy != GTADOC_TV_BOTTOM_UP && strategy != GTADOC_TV_TOP_DOWN)
     return fail(GTADOC_ERR_INVALID_ARG, "unknown term vector strategy %d", strategy);
+  if (int rl = ensure_levels(g, stream)) return rl;
   Call call(g->ctx, stream);
   int rc = call.begin();
   if (rc) return rc;
@@ -1052,6 +1159,7 @@ int inverted_index_run(gtadoc_grammar g, bool ranked, Call& call, gtadoc_result*
 
 int inverted_index_entry(gtadoc_grammar g, bool ranked, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
+  if (int rl = ensure_levels(g, stream)) return rl;
   Call call(g->ctx, stream);
   int rc = call.begin();
   if (rc) return rc;
@@ -1281,6 +1389,7 @@ int sequence_count_wide_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* 
 int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void* stream) {
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   if (n < 2 || n > 8) return fail(GTADOC_ERR_INVALID_ARG, "n must be in 2..8");
+  if (int rl = ensure_levels(g, stream)) return rl;
   Call call(g->ctx, stream);
   const int rc = call.begin();
   if (rc) return rc;
@@ -1291,6 +1400,7 @@ int gtadoc_sequence_count(gtadoc_grammar g, int n, gtadoc_result* out, void* str
   if (!g || !out) return fail(GTADOC_ERR_INVALID_ARG, "null argument");
   int rc = sequence_args(g, n);
   if (rc) return rc;
+  if ((rc = ensure_levels(g, stream))) return rc;
   Call call(g->ctx, stream);
   rc = call.begin();
   if (rc) return rc;
@@ -1334,6 +1444,10 @@ int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
       if (value < 1 || value > INT32_MAX) return fail(GTADOC_ERR_INVALID_ARG, "tail-level threshold out of range");
       ctx->level.tail_rules = (int32_t)value;
       return GTADOC_OK;
+    case GTADOC_PARAM_FLOW_KEEP:
+      if (value < 0 || value > 7168) return fail(GTADOC_ERR_INVALID_ARG, "ring threshold out of range (0..7168)");
+      ctx->level.flow_keep = (int32_t)value;
+      return GTADOC_OK;
     default:
       return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
@@ -1353,6 +1467,7 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value) {
     case GTADOC_PARAM_LEVEL_MID_RULES: *value = ctx->level.mid_rules; break;
     case GTADOC_PARAM_LEVEL_MID_BLOCKS: *value = ctx->level.mid_blocks; break;
     case GTADOC_PARAM_LEVEL_TAIL_RULES: *value = ctx->level.tail_rules; break;
+    case GTADOC_PARAM_FLOW_KEEP: *value = ctx->level.flow_keep; break;
     default: return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
   return GTADOC_OK;
@@ -1527,6 +1642,8 @@ int gtadoc_batch_submit(gtadoc_batch b, gtadoc_query* q, int nq, void* stream) {
   }
   if ((int)wc_g.size() > b->max_items)
     return fail(GTADOC_ERR_INVALID_ARG, "%d word counts exceed the plan (%d)", (int)wc_g.size(), b->max_items);
+  for (int i : other)  // grammars loaded without levels get them first (synchronizes once per grammar)
+    if (int rl = ensure_levels(q[i].grammar, stream)) return rl;
   for (int i = 0; i < nq; ++i) q[i].status = GTADOC_OK, q[i].result = nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
   // the other queries start after the context's earlier work, not after this batch's word counts
@@ -1616,7 +1733,10 @@ int gtadoc_query_bytes(gtadoc_grammar g, int kind, int n, int strategy, uint64_t
     return GTADOC_OK;
   }
   gtadoc_ctx ctx = g->ctx;
-  // sequence count's head/tail buffers belong to the grammar, not the query
+  // the level structure and sequence count's head/tail buffers belong to the
+  // grammar, not the query
+  if (kind != GTADOC_QUERY_WORD_COUNT)
+    if (int rl = ensure_levels(g, stream)) return rl;
   if (kind == GTADOC_QUERY_SEQUENCE_COUNT && !g->seq_len) {
     Call call(ctx, stream);
     int rc = call.begin();

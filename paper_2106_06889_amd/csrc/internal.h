@@ -64,6 +64,7 @@ enum : uint32_t {
   ST_BAD_WORD = 8u,      // word id >= vocab
   ST_BAD_REF = 16u,      // rule reference outside [1, R)
   ST_PACK = 32u,         // a weight >= 2^40 or an in-degree >= 2^24 (beyond the packed load word)
+  ST_FLOW = 64u,         // the dataflow walk ran out of queue room or waited past its bound (internal)
 };
 
 // Device view of a loaded grammar and its initialization-phase products.
@@ -137,8 +138,10 @@ hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_
 // in-degrees and initial weights (packed in g.w) from the reference entries
 // (after the offsets are scanned)
 hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s);
-// level 1 (rules no rule references) by compaction, then the level walk
-hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s);
+// level 1 (rules no rule references) by compaction into g.level_rule (and,
+// when qw is given, their weights into qw), then the level walk
+hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s,
+                                 uint64_t* qw = nullptr);
 hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, const WideBufs& wide,
                               hipStream_t s);
 // Launch shape of the level walk (context parameters, tunable):
@@ -147,16 +150,42 @@ hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* s
 //  mid_rules   levels narrower than this run on the first mid_blocks
 //              workgroups only (a cheaper barrier);
 //  tail_rules  levels narrower than this run on workgroup 0 alone.
+//  flow_keep   the dataflow walk keeps at most this many ready rules in a
+//              workgroup's ring at the end of a round and shares the rest.
 struct LevelParams {
   int32_t long_body = 32;
   int32_t mid_rules = 48 * 1024;
   int32_t mid_blocks = 32;
   int32_t tail_rules = 1024;
+  int32_t flow_keep = 4096;
 };
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
                              const WideBufs& wide, const LevelParams& params, int device, hipStream_t s);
 // after the walk: g.w[r] = weight of r (the pending fields are zero)
 hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s);
+
+// Dataflow walk (weights without levels): the global queue of ready rules
+// (level 1 first, as compacted into level_rule with its weights in qw) and
+// the descriptors of the chunks published into it; counters in FlowState
+// (set up by the launcher from lc->frontier0).
+struct FlowState {
+  int64_t live;       // rules queued anywhere or being walked
+  int64_t n1;         // rules of level 1
+  uint32_t space;     // queue entries reserved (level 1 first)
+  uint32_t ticket;    // next chunk ticket
+  uint32_t nspill;    // chunks published beyond level 1
+  uint32_t nchunks0;  // chunks of level 1
+};
+struct FlowBufs {
+  int32_t* qc;     // [qcap] rules (level_rule)
+  uint64_t* qw;    // [qcap] their final weights
+  uint64_t* desc;  // [ndesc] published chunks: start << 16 | count, 0 = not yet
+  uint32_t qcap, ndesc;
+};
+// placed and tokens are added to lc (zero before); g.w holds packed words
+// on entry and unpacks like after the level walk
+hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb,
+                            const LevelParams& lp, int device, hipStream_t s);
 
 // word count and sort
 hipError_t launch_word_count(const DevGrammar& g, uint64_t* counts, hipStream_t s);   // direct atomics

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_zero_count(const uint64_t* pw, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t R, const uint32_t* off,
-                                                    int32_t* out) {
+                                                    int32_t* out, uint64_t* qw) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
   uint32_t c = 0;
   bool z[16];
@@ -59,7 +59,10 @@ __global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t 
   uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (z[k]) out[pos++] = (int32_t)(i0 + k);
+    if (z[k]) {
+      if (qw) qw[pos] = pw[i0 + k] >> kPendBits;
+      out[pos++] = (int32_t)(i0 + k);
+    }
 }
 
 // The level walk (one cooperative launch, one 1024-thread workgroup per CU).
@@ -499,7 +502,8 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
   }
 }
 
-hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s) {
+hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s,
+                                 uint64_t* qw) {
   // level 1 by compaction (scratch: per-block counts, then the scan's block sums)
   const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
   k_zero_count<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch);
@@ -507,7 +511,7 @@ hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t
   if (e != hipSuccess) return e;
   e = launch_scan_u32(scratch, nb, &lc->frontier0, scratch + nb, s);
   if (e != hipSuccess) return e;
-  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch, g.level_rule);
+  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch, g.level_rule, qw);
   return hipGetLastError();
 }
 

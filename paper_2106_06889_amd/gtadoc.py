@@ -22,7 +22,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "gtadoc.h")
 
 OK = 0
 ERR_INVALID_ARG, ERR_BAD_GRAMMAR, ERR_CYCLE, ERR_OOM, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_HIP = range(-1, -8, -1)
-IN_HOST, IN_DEVICE, IN_BORROW = 0x1, 0x2, 0x4
+IN_HOST, IN_DEVICE, IN_BORROW, LOAD_LEVELS = 0x1, 0x2, 0x4, 0x8
 _NAMES = {-1: "INVALID_ARG", -2: "BAD_GRAMMAR", -3: "CYCLE", -4: "OOM", -5: "UNSUPPORTED", -6: "OVERFLOW", -7: "HIP"}
 
 
@@ -52,6 +52,7 @@ EXPORTS = {
     "gtadoc_ctx_usage": [_vp, _vp, _vp, _vp],
     "gtadoc_load_grammar": [_vp, _vp, _i64, _vp, _i64, _vp, _i64, _i32, _u32, _vp, _vp],
     "gtadoc_grammar_stats": [_vp, _vp],
+    "gtadoc_build_levels": [_vp, _vp],
     "gtadoc_grammar_edges": [_vp, _vp, _vp],
     "gtadoc_query_bytes": [_vp, _int, _int, _int, _vp, _vp],
     "gtadoc_free_grammar": [_vp],
@@ -81,6 +82,7 @@ EXPORTS = {
 }
 PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING, PARAM_LEVEL_WIDE = 1, 2, 3, 4, 5
 PARAM_LEVEL_LONG_BODY, PARAM_LEVEL_MID_RULES, PARAM_LEVEL_MID_BLOCKS, PARAM_LEVEL_TAIL_RULES = 6, 7, 8, 9
+PARAM_FLOW_KEEP = 10
 PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6,
           "decompress": 7, "tv_topdown": 8}
 TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN = 0, 1, 2
@@ -182,8 +184,12 @@ class Context:
         _check(lib().gtadoc_ctx_usage(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
-    def load(self, rule_off, sym, file_off, vocab: int, stream=None, borrow: bool = False) -> "Grammar":
-        """Load a grammar from numpy arrays (host) or torch device tensors."""
+    def load(self, rule_off, sym, file_off, vocab: int, stream=None, borrow: bool = False,
+             levels: bool = False) -> "Grammar":
+        """Load a grammar from numpy arrays (host) or torch device tensors.
+        levels=True builds the level structure during the load (level walk);
+        otherwise the weights come from the dataflow walk and the levels are
+        built when a query first needs them."""
         keep = ()
         if isinstance(sym, torch.Tensor):
             rule_off = rule_off.to(torch.int64).contiguous()
@@ -198,6 +204,8 @@ class Context:
             file_off = np.ascontiguousarray(file_off, dtype=np.int64)
             flags = IN_HOST
             ptrs = (rule_off.ctypes.data, sym.ctypes.data if sym.size else None, file_off.ctypes.data)
+        if levels:
+            flags |= LOAD_LEVELS
         R, S, F = len(rule_off) - 1, len(sym), len(file_off) - 1
         h = _vp()
         with torch.cuda.device(self.device):
@@ -245,6 +253,15 @@ class Grammar:
             self.free()
         except Exception:
             pass
+
+    def build_levels(self, stream=None) -> int:
+        """Builds the level structure if the load did not; returns the depth
+        (also refreshed in self.stats)."""
+        _check(lib().gtadoc_build_levels(self.handle, _stream_ptr(stream)))
+        st = Stats()
+        _check(lib().gtadoc_grammar_stats(self.handle, ctypes.byref(st)))
+        self.stats = st.as_dict()
+        return int(self.stats["depth"])
 
     def word_count(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """uint64 counts as an int64 tensor of vocab entries (bit pattern = uint64)."""

@@ -35,9 +35,10 @@ def _write_record(root, src_text, sha=None):
 def test_traffic_record_matches_sources(tmp_path, monkeypatch):
     _write_record(str(tmp_path), "kernel v1")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("levels", "wc-100m") == 12345
-    assert bench.measured_traffic("levels", "seq-20m") is None      # another workload
-    assert bench.measured_traffic("word_count", "wc-100m") is None  # no record for that kernel
+    assert bench.measured_traffic("k_levels", "wc-100m") == 12345
+    assert bench.measured_traffic("k_levels", "seq-20m") is None    # another workload
+    assert bench.measured_traffic("k_flow", "wc-100m") is None      # no record for that kernel
+    assert bench.measured_traffic(None, "wc-100m") is None
 
 
 def test_traffic_record_dropped_after_a_source_change(tmp_path, monkeypatch):
@@ -45,5 +46,5 @@ def test_traffic_record_dropped_after_a_source_change(tmp_path, monkeypatch):
     with open(os.path.join(str(tmp_path), "k", "kernel.hip"), "a") as f:
         f.write("// changed\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("levels", "wc-100m") is None
+    assert bench.measured_traffic("k_levels", "wc-100m") is None
 

@@ -99,7 +99,7 @@ def test_uncompressed_analytics_match_oracle(ctx):
     tok, off = G.decompress()
     P = plain_grammar(ctx, tok, off, g.vocab)
     try:
-        assert P.stats["tokens"] == len(c.tokens) and P.stats["depth"] == 0
+        assert P.stats["tokens"] == len(c.tokens) and P.build_levels() == 0
         assert np.array_equal(gt.to_u64(P.word_count()), oracle.wc_text(c.tokens, g.vocab))
         res = P.term_vector()
         got = (res.arrays[0].cpu().numpy(), res.arrays[1].cpu().numpy().view(np.uint32), gt.to_u64(res.arrays[2]))

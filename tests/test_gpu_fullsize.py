@@ -50,7 +50,7 @@ def test_seq_20m_full(ctx):
     c, g = synth.workload("seq-20m")
     T = len(c.tokens)
     del c
-    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab, levels=True)
     assert G.stats["depth"] >= 40
     for n in (2, 3):
         res = G.sequence_count(n)

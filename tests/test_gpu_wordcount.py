@@ -31,27 +31,36 @@ def gold(name):
 
 
 def check_wc_sort(ctx, g, expect_tokens=None):
+    """Word count and sort against the oracle after both loads: the dataflow
+    walk (levels built afterwards) and the level walk during the load; their
+    figures agree. Returns the stats (depth included)."""
     import paper_2106_06889_amd as gt
-    G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
-    try:
-        want = oracle.traverse_word_count(g)
-        got = gt.to_u64(G.word_count())
-        assert np.array_equal(got, want)
-        assert G.stats["tokens"] == int(want.sum())
-        if expect_tokens is not None:
-            assert G.stats["tokens"] == expect_tokens
-        wid, wcnt = oracle.sort_counts(want)
-        ids, cnt, num = G.sort()
-        k = int(num.item())
-        assert k == len(wid)
-        assert np.array_equal(ids[:k].cpu().numpy().view(np.uint32), wid)
-        assert np.array_equal(gt.to_u64(cnt[:k]), wcnt)
-        # sort from precomputed counts gives the same
-        ids2, cnt2, num2 = G.sort(word_counts=G.word_count())
-        assert int(num2.item()) == k and np.array_equal(ids2[:k].cpu().numpy(), ids[:k].cpu().numpy())
-        return G.stats
-    finally:
-        G.free()
+    want = oracle.traverse_word_count(g)
+    wid, wcnt = oracle.sort_counts(want)
+    stats = []
+    for levels in (False, True):
+        G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab, levels=levels)
+        try:
+            assert (G.stats["depth"] == -1) != levels
+            got = gt.to_u64(G.word_count())
+            assert np.array_equal(got, want), levels
+            assert G.stats["tokens"] == int(want.sum())
+            if expect_tokens is not None:
+                assert G.stats["tokens"] == expect_tokens
+            ids, cnt, num = G.sort()
+            k = int(num.item())
+            assert k == len(wid)
+            assert np.array_equal(ids[:k].cpu().numpy().view(np.uint32), wid)
+            assert np.array_equal(gt.to_u64(cnt[:k]), wcnt)
+            # sort from precomputed counts gives the same
+            ids2, cnt2, num2 = G.sort(word_counts=G.word_count())
+            assert int(num2.item()) == k and np.array_equal(ids2[:k].cpu().numpy(), ids[:k].cpu().numpy())
+            G.build_levels()
+            stats.append(G.stats)
+        finally:
+            G.free()
+    assert stats[0] == stats[1]
+    return stats[1]
 
 
 @pytest.mark.parametrize("name", ["e1_sequitur_abcdbc.json", "e2_two_files.json", "e3_head_tail.json"])
@@ -155,9 +164,10 @@ def test_rejects_bad_grammars(ctx):
     }
     before = ctx.usage()[0]
     for name, (ro, sym, fo, code) in cases.items():
-        with pytest.raises(gt.GtadocError) as e:
-            ctx.load(ro, sym, fo, V)
-        assert e.value.code == code, name
+        for levels in (False, True):
+            with pytest.raises(gt.GtadocError) as e:
+                ctx.load(ro, sym, fo, V, levels=levels)
+            assert e.value.code == code, (name, levels)
     assert ctx.usage()[0] == before  # nothing leaked
 
 
@@ -190,6 +200,58 @@ def test_vocabulary_beyond_bucket_table(ctx):
     tok = rng.choice(np.array([0, 7, V - 1, 1 << 20, (1 << 24) + 1], np.int64), size=3000).astype(np.int32)
     g = synth.compress(tok, np.array([0, 1000, 3000], np.int64), V)
     check_wc_sort(ctx, g, expect_tokens=3000)
+
+
+@pytest.mark.parametrize("keep,long_body", [(0, 32), (64, 1), (4096, 8), (7168, 1 << 20)])
+def test_dataflow_walk_shapes(ctx, keep, long_body):
+    """The dataflow walk with rings that share everything beyond 0 or 64
+    rules (many published chunks), bodies walked by waves from 1 symbol or
+    never: the same counts as the oracle on recipe-scaled corpora and random
+    ones."""
+    import paper_2106_06889_amd as gt
+    cases = [synth.workload("wc-100m", scale=0.02), synth.workload("seq-20m", scale=0.02),
+             synth.workload("tv-4000files", scale=0.005)]
+    for seed in (6, 7):
+        c = synth.random_corpus(seed, 2, 5000, [40, 900][seed % 2])
+        cases.append((c, synth.compress(c.tokens, c.file_off, c.vocab)))
+    old = ctx.get_param(gt.PARAM_FLOW_KEEP), ctx.get_param(gt.PARAM_LEVEL_LONG_BODY)
+    ctx.set_param(gt.PARAM_FLOW_KEEP, keep)
+    ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, long_body)
+    try:
+        for c, g in cases:
+            G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
+            try:
+                assert np.array_equal(gt.to_u64(G.word_count()), oracle.traverse_word_count(g))
+                assert G.stats["tokens"] == len(c.tokens)
+            finally:
+                G.free()
+    finally:
+        ctx.set_param(gt.PARAM_FLOW_KEEP, old[0])
+        ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, old[1])
+
+
+def test_dataflow_ring_overflow(ctx):
+    """One rule readies 20,000 sub-rules at once (each used only by it), far
+    more than a workgroup's ring holds: the overflow goes to the shared queue
+    as chunks of the readying waves. Also a second parent for half of them,
+    so their last in-edge arrives from another rule."""
+    import paper_2106_06889_amd as gt
+    K, V = 20000, 11
+    root = np.array([-1, 0, -1, -2], np.int32)        # rule 1 twice, rule 2 once
+    body1 = -np.arange(3, 3 + K, dtype=np.int32)         # rules 3 .. K+2
+    body2 = -np.arange(3, 3 + K, 2, dtype=np.int32)      # every other one again
+    leaves = [np.array([r % V, (r * 7) % V], np.int32) for r in range(K)]
+    bodies = [root, body1, body2] + leaves
+    rule_off = np.cumsum([0] + [len(b) for b in bodies]).astype(np.int64)
+    g = synth.Grammar(rule_off, np.concatenate(bodies), np.array([0, 4], np.int64), V)
+    assert oracle.check_structure(g) == 0
+    for long_body in (32, 1 << 20):  # walked by a wave, or by one thread
+        old = ctx.get_param(gt.PARAM_LEVEL_LONG_BODY)
+        ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, long_body)
+        try:
+            check_wc_sort(ctx, g)
+        finally:
+            ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, old)
 
 
 def test_deep_chain(ctx):
