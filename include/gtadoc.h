@@ -288,8 +288,10 @@ int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void
 #define GTADOC_PARAM_LEVEL_MID_BLOCKS 8 /* load: workgroups of the narrower levels (1..256); default 32 */
 #define GTADOC_PARAM_LEVEL_TAIL_RULES 9 /* load: levels narrower than this run on one workgroup; default 1024 */
 #define GTADOC_PARAM_FLOW_KEEP 10       /* load, dataflow walk: ready rules a workgroup keeps in its ring at
-                                          the end of a round; the rest go to the shared queue (0..7168;
-                                          default 4096) */
+                                          the end of a round, per 1024 threads; the rest go to the shared
+                                          queue (0..7168; default 4096) */
+#define GTADOC_PARAM_FLOW_GROUP 11      /* load, dataflow walk: threads per workgroup, 512 (two per CU) or
+                                          1024 (default) */
 
 /* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);

@@ -151,13 +151,17 @@ hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* s
 //              workgroups only (a cheaper barrier);
 //  tail_rules  levels narrower than this run on workgroup 0 alone.
 //  flow_keep   the dataflow walk keeps at most this many ready rules in a
-//              workgroup's ring at the end of a round and shares the rest.
+//              workgroup's ring at the end of a round and shares the rest
+//              (per 1024 threads);
+//  flow_group  threads per workgroup of the dataflow walk (512: two
+//              workgroups per CU, or 1024).
 struct LevelParams {
   int32_t long_body = 32;
   int32_t mid_rules = 48 * 1024;
   int32_t mid_blocks = 32;
   int32_t tail_rules = 1024;
   int32_t flow_keep = 4096;
+  int32_t flow_group = 1024;
 };
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
                              const WideBufs& wide, const LevelParams& params, int device, hipStream_t s);

@@ -20,14 +20,23 @@
 // a list round trip per level. Levels (longest path from the root) are not
 // produced; queries that need them build them with the level walk.
 //
-// Work sharing. Each workgroup runs rounds of at most kFlowThreads rules,
-// one per thread (bodies longer than `long_body` symbols are walked by a
-// whole wave, lanes across the body). A round takes its rules from the LDS
-// ring; a workgroup whose ring is empty takes a ticket for one chunk of a
-// global queue. The queue starts with level 1 (the rules without pending
-// in-edges, in chunks of kFlowThreads) and grows by chunks that workgroups
-// publish when their ring holds more than `keep` rules, or when a round
-// readies more rules than the ring holds. A published chunk is a range of
+// Rounds. Each workgroup runs rounds of at most kT rules (its thread count).
+// A round's bodies are walked position-parallel: every thread loads one
+// rule's offsets, a block scan of the body lengths places the round's
+// symbols on one axis, and each thread takes symbols t, t + kT, ... (found
+// back to their rule by binary search in LDS), 8 at a time, issuing all 8
+// atomics before it looks at any result. A round costs about the same for a
+// 2-symbol body and a 300-symbol one, and neighbouring threads read
+// neighbouring symbols.
+//
+// Work sharing. A round takes rules from the workgroup's LDS ring first,
+// then from a held range of a global queue. The queue starts with level 1
+// (the rules without pending in-edges, in chunks of kFlowChunk0) and grows by
+// chunks that workgroups publish when their ring holds more than `keep`
+// rules, or when a round readies more rules than the ring holds. Tickets hand out the
+// chunks in order: a workgroup takes the next one when its range is used up
+// and its ring holds less than a round, and keeps working from its ring
+// until a published chunk is there. A published chunk is a range of
 // the queue's (rule, weight) arrays plus a descriptor, stored with release
 // order after the entries; the ticket holder polls the descriptor and
 // acquires. Termination: `live` counts the rules queued anywhere or being
@@ -42,28 +51,33 @@
 
 namespace gt {
 
-constexpr int kFlowThreads = 1024;
-constexpr int kFlowRing = 8192;  // power of two
+constexpr int kFlowChunk0 = 1024;  // rules per level-1 chunk
 constexpr uint32_t kFlowSpinLimit = 1u << 21;
 
+template <int kT>
 struct FlowLds {
-  int32_t rc[kFlowRing];  // ring of ready rules and their final weights
-  uint64_t rw[kFlowRing];
-  int32_t lc[kFlowThreads];  // long bodies of the round
-  uint64_t lw[kFlowThreads];
-  uint32_t head, tail;  // ring cursors: entries [head, tail), slot = cursor mod kFlowRing
-  uint32_t take_at;     // ring cursor of the round's first rule
-  int32_t n;            // rules of the round (-1: leave)
-  int32_t src;          // 0: ring, 1: global queue at gstart
-  uint32_t gstart;
-  uint32_t pushed;  // rules readied into the ring in the round
-  int32_t nlong;
+  static constexpr int kRing = 8 * kT;  // power of two
+  int32_t rc[kRing];  // ring of ready rules and their final weights
+  uint64_t rw[kRing];
+  int64_t ra[kT];        // the round's rules: body start,
+  uint64_t rwt[kT];      // weight,
+  uint32_t roff[kT + 1];  // and first position on the round's symbol axis
+  uint32_t scan[kT / 64 + 1];
+  uint32_t head, tail;   // ring cursors: entries [head, tail), slot = cursor mod kRing
+  uint32_t take_at;      // ring part of the round: [take_at, take_at + n - nglob)
+  uint32_t gpos, gleft;  // held range of the global queue
+  uint32_t gtake, nglob;  // global part of the round: [gtake, gtake + nglob)
+  int64_t ticket;        // ticket whose chunk has not arrived (-1: none)
+  int64_t n1;            // rules of level 1
+  uint32_t n0;           // level-1 chunks
+  int32_t n;             // rules of the round (-1: leave)
+  uint32_t pushed;       // rules readied into the ring in the round
   uint32_t sp_base, sp_n, sp_from;  // spill of the ring's excess at round end
-  uint64_t part[kFlowThreads / 64];
+  uint64_t part[kT / 64];
 };
 
-// Publishes queue entries [base, base + n) (already stored by this wave or,
-// after a block barrier, by the workgroup) as one chunk.
+// Publishes queue entries [base, base + n) (already stored, with release
+// order, by this wave or the workgroup) as one chunk.
 __device__ __forceinline__ void flow_publish(FlowState* fs, const FlowBufs& fb, uint32_t* status, uint32_t base,
                                              uint32_t n) {
   const uint32_t j = atomicAdd(&fs->nspill, 1u);
@@ -76,8 +90,10 @@ __device__ __forceinline__ void flow_publish(FlowState* fs, const FlowBufs& fb, 
 
 // Readied rules of one wave step: into the ring while it has room, the rest
 // straight to the global queue as one chunk of this wave.
-__device__ __forceinline__ void flow_push(FlowLds& L, FlowState* fs, const FlowBufs& fb, uint32_t* status, bool ready,
-                                          int32_t c, uint64_t w) {
+template <int kT>
+__device__ __forceinline__ void flow_push(FlowLds<kT>& L, FlowState* fs, const FlowBufs& fb, uint32_t* status,
+                                          bool ready, int32_t c, uint64_t w) {
+  constexpr uint32_t kRing = FlowLds<kT>::kRing;
   const uint64_t mask = __ballot(ready);
   if (!mask) return;
   const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -85,7 +101,7 @@ __device__ __forceinline__ void flow_push(FlowLds& L, FlowState* fs, const FlowB
   uint32_t base = 0, room = 0;
   if (lane_id() == leader) {
     base = atomicAdd(&L.tail, n);
-    const uint32_t lim = L.head + kFlowRing;  // head does not move while rules are walked
+    const uint32_t lim = L.head + kRing;  // head does not move while rules are walked
     room = (int32_t)(lim - base) <= 0 ? 0u : (lim - base < n ? lim - base : n);
     if (room < n) atomicSub(&L.tail, n - room);  // only the wave that crosses the limit keeps a part
     if (room) atomicAdd(&L.pushed, room);          // counted in `live` at the end of the round
@@ -94,7 +110,7 @@ __device__ __forceinline__ void flow_push(FlowLds& L, FlowState* fs, const FlowB
   room = __shfl(room, leader);
   const uint32_t rank = (uint32_t)__popcll(mask & lanes_below());
   if (ready && rank < room) {
-    const uint32_t slot = (base + rank) & (kFlowRing - 1);
+    const uint32_t slot = (base + rank) & (kRing - 1);
     L.rc[slot] = c;
     L.rw[slot] = w;
   }
@@ -120,46 +136,37 @@ __device__ __forceinline__ void flow_push(FlowLds& L, FlowState* fs, const FlowB
   }
 }
 
-// Retires one in-edge of rule c with weight w of the parent; returns the old
-// packed word.
-__device__ __forceinline__ uint64_t flow_retire(uint64_t* pw, int32_t c, uint64_t w) {
-  return atomicAdd(reinterpret_cast<unsigned long long*>(&pw[c]), (unsigned long long)((w << kPendBits) - 1u));
-}
-
-// The round's source, chosen by thread 0: the ring, else a ticket of the
-// global queue (waiting until its chunk is published or no work is left).
-__device__ __forceinline__ void flow_decide(FlowLds& L, FlowState* fs, const FlowBufs& fb, uint32_t* status) {
-  const uint32_t occ = L.tail - L.head;
-  if (occ) {
-    const uint32_t n = occ < (uint32_t)kFlowThreads ? occ : (uint32_t)kFlowThreads;
-    L.take_at = L.head;
-    L.head += n;
-    L.n = (int32_t)n;
-    L.src = 0;
-    return;
-  }
-  const uint32_t j = atomicAdd(&fs->ticket, 1u);
-  const uint32_t n0 = fs->nchunks0;
-  if (j < n0) {
-    const int64_t st = (int64_t)j * kFlowThreads;
-    const int64_t left = fs->n1 - st;
-    L.gstart = (uint32_t)st;
-    L.n = (int32_t)(left < kFlowThreads ? left : kFlowThreads);
-    L.src = 1;
-    return;
-  }
-  const uint32_t k = j - n0;
+// The round's rules, chosen by thread 0: ring entries first (the deeper
+// rules, so chains of sub-rules move on as early as possible), then the held
+// global range. When the range is used up and the ring holds less than a
+// round, a ticket is taken; a level-1 chunk is there at once, a later one is
+// picked up once its descriptor is published. With neither ring entries nor
+// a range the workgroup waits for its chunk, or leaves when no work is left.
+template <int kT>
+__device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const FlowBufs& fb, uint32_t* status) {
+  const uint32_t n0 = L.n0;
   for (uint32_t it = 0;; ++it) {
-    if (k < fb.ndesc) {
-      const uint64_t v = __hip_atomic_load(&fb.desc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        L.gstart = (uint32_t)(v >> 16);
-        L.n = (int32_t)(v & 0xffffu);
-        L.src = 1;
-        return;
+    if (L.gleft == 0) {
+      if (L.ticket < 0 && L.tail - L.head < (uint32_t)kT) L.ticket = atomicAdd(&fs->ticket, 1u);
+      if (L.ticket >= 0) {
+        const uint32_t j = (uint32_t)L.ticket;
+        if (j < n0) {
+          const int64_t st = (int64_t)j * kFlowChunk0, left = L.n1 - st;
+          L.gpos = (uint32_t)st;
+          L.gleft = (uint32_t)(left < kFlowChunk0 ? left : kFlowChunk0);
+          L.ticket = -1;
+        } else if (j - n0 < fb.ndesc) {
+          const uint64_t v = __hip_atomic_load(&fb.desc[j - n0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (v) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            L.gpos = (uint32_t)(v >> 16);
+            L.gleft = (uint32_t)(v & 0xffffu);
+            L.ticket = -1;
+          }
+        }
       }
     }
+    if (L.tail != L.head || L.gleft) break;
     // zero only once every rule has been walked: the chunk will never come
     if (__hip_atomic_load(&fs->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       L.n = -1;
@@ -172,14 +179,61 @@ __device__ __forceinline__ void flow_decide(FlowLds& L, FlowState* fs, const Flo
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  const uint32_t occ = L.tail - L.head;
+  const uint32_t nr = occ < (uint32_t)kT ? occ : (uint32_t)kT;
+  L.take_at = L.head;
+  L.head += nr;
+  const uint32_t ng = L.gleft < (uint32_t)kT - nr ? L.gleft : (uint32_t)kT - nr;
+  L.gtake = L.gpos;
+  L.gpos += ng;
+  L.gleft -= ng;
+  L.nglob = ng;
+  L.n = (int32_t)(nr + ng);
 }
 
-__global__ __launch_bounds__(kFlowThreads) void k_flow(DevGrammar g, LoadCounters* lc, FlowState* fs, FlowBufs fb,
-                                                       int32_t long_body, int32_t keep) {
-  __shared__ FlowLds L;
+// Exclusive scan of v over the workgroup; *total = the sum.
+template <int kT>
+__device__ __forceinline__ uint32_t flow_scan(uint32_t v, FlowLds<kT>& L, uint32_t* total) {
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane_id() >= d) x += y;
+  }
+  const int wv = threadIdx.x >> 6;
+  if (lane_id() == 63) L.scan[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int k = 0; k < kT / 64; ++k) {
+      const uint32_t q = L.scan[k];
+      L.scan[k] = s;
+      s += q;
+    }
+    L.scan[kT / 64] = s;
+  }
+  __syncthreads();
+  *total = L.scan[kT / 64];
+  return L.scan[wv] + x - v;
+}
+
+// Retires one in-edge of rule c with weight w of the parent; returns the old
+// packed word.
+__device__ __forceinline__ uint64_t flow_retire(uint64_t* pw, int32_t c, uint64_t w) {
+  return atomicAdd(reinterpret_cast<unsigned long long*>(&pw[c]), (unsigned long long)((w << kPendBits) - 1u));
+}
+
+template <int kT>
+__global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, FlowState* fs, FlowBufs fb, int32_t keep) {
+  constexpr uint32_t kRing = FlowLds<kT>::kRing;
+  __shared__ FlowLds<kT> L;
   uint32_t* status = &lc->status;
   const int t = threadIdx.x;
-  if (t == 0) L.head = 0, L.tail = 0, L.pushed = 0, L.nlong = 0, L.sp_n = 0;
+  if (t == 0) {
+    L.head = 0, L.tail = 0, L.pushed = 0, L.sp_n = 0, L.gleft = 0, L.gpos = 0, L.ticket = -1;
+    L.n1 = fs->n1;
+    L.n0 = fs->nchunks0;
+  }
   uint64_t tokens = 0;
   int64_t walked = 0;  // thread 0
   __syncthreads();
@@ -188,84 +242,77 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow(DevGrammar g, LoadCounter
     __syncthreads();
     const int32_t n = L.n;
     if (n < 0) break;
+    const uint32_t nr = (uint32_t)n - L.nglob;
     int32_t c = -1;
     uint64_t w = 0;
-    if (t < n) {
-      if (L.src == 0) {
-        const uint32_t slot = (L.take_at + (uint32_t)t) & (kFlowRing - 1);
-        c = L.rc[slot];
-        w = L.rw[slot];
-      } else {
-        c = fb.qc[L.gstart + t];
-        w = fb.qw[L.gstart + t];
-      }
+    if ((uint32_t)t < nr) {
+      const uint32_t slot = (L.take_at + (uint32_t)t) & (kRing - 1);
+      c = L.rc[slot];
+      w = L.rw[slot];
+    } else if (t < n) {
+      const uint32_t i = L.gtake + ((uint32_t)t - nr);
+      c = fb.qc[i];
+      w = fb.qw[i];
     }
-    __syncthreads();  // the round's ring slots are read before pushes reuse them
+    int64_t a = 0;
+    uint32_t len = 0;
     if (c > 0 && c < g.R) {
-      const int64_t a = g.rule_off[c], e = g.rule_off[c + 1];
-      if (e - a > long_body) {
-        const int k = atomicAdd(&L.nlong, 1);
-        L.lc[k] = c;
-        L.lw[k] = w;
-      } else {
-        uint64_t words = 0;
-        for (int64_t q0 = a; q0 < e; q0 += 8) {
-          int32_t v[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) v[k] = q0 + k < e ? g.sym[q0 + k] : 0;
-          uint64_t old[8];
-          int32_t cs[8];
-          bool ref[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {  // every atomic of the group is issued before any result is used
-            ref[k] = false;
-            cs[k] = 0;
-            old[k] = 0;
-            if (q0 + k >= e) continue;
-            if (v[k] >= 0) {
-              ++words;
-            } else if (-(int64_t)v[k] < g.R) {
-              cs[k] = (int32_t)(-(int64_t)v[k]);
-              ref[k] = true;
-              old[k] = flow_retire(g.w, cs[k], w);
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            if (ref[k] && (old[k] >> kPendBits) + w >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
-            flow_push(L, fs, fb, status, ref[k] && (old[k] & kPendMask) == 1, cs[k], (old[k] >> kPendBits) + w);
-          }
-        }
-        tokens += words * w;
-      }
+      a = g.rule_off[c];
+      len = (uint32_t)(g.rule_off[c + 1] - a);
     }
+    uint32_t total;
+    const uint32_t off = flow_scan(len, L, &total);  // its barriers also free the round's ring slots
+    if (t < n) {
+      L.ra[t] = a;
+      L.rwt[t] = w;
+      L.roff[t] = off;
+    }
+    if (t == 0) L.roff[n] = total;
     __syncthreads();
-    const int nl = L.nlong;
-    for (int j = t >> 6; j < nl; j += kFlowThreads >> 6) {
-      const int32_t p = L.lc[j];
-      const uint64_t wp = L.lw[j];
-      const int64_t e = g.rule_off[p + 1];
-      int64_t q = g.rule_off[p] + lane_id();
-      int32_t cur = q < e ? g.sym[q] : 0;
-      uint64_t words = 0;
-      for (; q < e; q += 64) {
-        const int32_t nxt = q + 64 < e ? g.sym[q + 64] : 0;  // next load in flight while this one is used
-        bool ready = false;
-        int32_t cc = 0;
-        uint64_t nw = 0;
-        if (cur >= 0) {
-          ++words;
-        } else if (-(int64_t)cur < g.R) {
-          cc = (int32_t)(-(int64_t)cur);
-          const uint64_t old = flow_retire(g.w, cc, wp);
-          if ((old >> kPendBits) + wp >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
-          ready = (old & kPendMask) == 1;
-          nw = (old >> kPendBits) + wp;
+    // the round's symbols, 8 per thread at a time
+    int step = 1;
+    while (step * 2 <= n) step *= 2;
+    for (uint32_t p0 = 0; p0 < total; p0 += 8u * kT) {
+      int32_t ri[8], v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ri[k] = 0;
+      for (int s2 = step; s2 >= 1; s2 >>= 1) {  // rule of each position: last roff <= p
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t p = p0 + (uint32_t)(k * kT + t);
+          if (ri[k] + s2 < n && L.roff[ri[k] + s2] <= p) ri[k] += s2;
         }
-        flow_push(L, fs, fb, status, ready, cc, nw);
-        cur = nxt;
       }
-      tokens += words * wp;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t p = p0 + (uint32_t)(k * kT + t);
+        v[k] = p < total ? g.sym[L.ra[ri[k]] + (p - L.roff[ri[k]])] : 0;
+      }
+      uint64_t old[8], wr[8];
+      int32_t cs[8];
+      bool ref[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {  // every atomic of the group is issued before any result is used
+        const uint32_t p = p0 + (uint32_t)(k * kT + t);
+        ref[k] = false;
+        cs[k] = 0;
+        old[k] = 0;
+        wr[k] = 0;
+        if (p >= total) continue;
+        wr[k] = L.rwt[ri[k]];
+        if (v[k] >= 0) {
+          tokens += wr[k];
+        } else if (-(int64_t)v[k] < g.R) {
+          cs[k] = (int32_t)(-(int64_t)v[k]);
+          ref[k] = true;
+          old[k] = flow_retire(g.w, cs[k], wr[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (ref[k] && (old[k] >> kPendBits) + wr[k] >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
+        flow_push(L, fs, fb, status, ref[k] && (old[k] & kPendMask) == 1, cs[k], (old[k] >> kPendBits) + wr[k]);
+      }
     }
     __syncthreads();
     if (t == 0) {
@@ -274,11 +321,10 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow(DevGrammar g, LoadCounter
       if (delta) atomicAdd(reinterpret_cast<unsigned long long*>(&fs->live), (unsigned long long)delta);
       walked += n;
       L.pushed = 0;
-      L.nlong = 0;
       L.sp_n = 0;
       const uint32_t occ = L.tail - L.head;
       if (occ > (uint32_t)keep) {
-        const uint32_t sn = occ - (uint32_t)keep < (uint32_t)kFlowThreads ? occ - (uint32_t)keep : (uint32_t)kFlowThreads;
+        const uint32_t sn = occ - (uint32_t)keep < (uint32_t)kT ? occ - (uint32_t)keep : (uint32_t)kT;
         const uint32_t base = atomicAdd(&fs->space, sn);
         if ((uint64_t)base + sn <= fb.qcap) {
           L.sp_base = base;
@@ -294,7 +340,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow(DevGrammar g, LoadCounter
     if (sn) {
       // the newest `sn` ring entries become a chunk of the global queue
       if ((uint32_t)t < sn) {
-        const uint32_t slot = (L.sp_from + (uint32_t)t) & (kFlowRing - 1);
+        const uint32_t slot = (L.sp_from + (uint32_t)t) & (kRing - 1);
         fb.qc[L.sp_base + t] = L.rc[slot];
         fb.qw[L.sp_base + t] = L.rw[slot];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the waves that stored
@@ -313,7 +359,7 @@ __global__ __launch_bounds__(kFlowThreads) void k_flow(DevGrammar g, LoadCounter
   __syncthreads();
   if (t == 0) {
     uint64_t sum = 0;
-    for (int k = 0; k < kFlowThreads / 64; ++k) sum += L.part[k];
+    for (int k = 0; k < kT / 64; ++k) sum += L.part[k];
     if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&lc->tokens), (unsigned long long)sum);
     if (walked) atomicAdd(&lc->placed, (int32_t)walked);
   }
@@ -323,11 +369,27 @@ __global__ void k_flow_init(const LoadCounters* lc, FlowState* fs) {
   if (threadIdx.x != 0) return;
   const int64_t n1 = lc->frontier0;
   fs->n1 = n1;
-  fs->nchunks0 = (uint32_t)((n1 + kFlowThreads - 1) / kFlowThreads);
+  fs->nchunks0 = (uint32_t)((n1 + kFlowChunk0 - 1) / kFlowChunk0);
   fs->live = n1;
   fs->space = (uint32_t)n1;
   fs->ticket = 0;
   fs->nspill = 0;
+}
+
+template <int kT>
+hipError_t launch_flow_kernel(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb, int32_t keep,
+                              int device, hipStream_t s) {
+  int cus = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  constexpr int kPerCu = 1024 / kT;  // workgroups that fit a CU together (LDS)
+  const int64_t want = (g.R + kT - 1) / kT;
+  const int64_t cap = (int64_t)(cus > 0 ? cus : 1) * kPerCu;
+  const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
+  const int32_t k = keep < 0 ? 0 : (keep > FlowLds<kT>::kRing - kT ? FlowLds<kT>::kRing - kT : keep);
+  // no workgroup holds work while it waits, so the walk needs no co-residency
+  k_flow<kT><<<grid, kT, 0, s>>>(g, lc, fs, fb, k);
+  return hipGetLastError();
 }
 
 hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb,
@@ -337,16 +399,8 @@ hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs
   k_flow_init<<<1, 64, 0, s>>>(lc, fs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int cus = 0;
-  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  if (e != hipSuccess) return e;
-  const int64_t want = (g.R + kFlowThreads - 1) / kFlowThreads;
-  const int64_t cap = cus > 0 ? cus : 1;
-  const unsigned grid = (unsigned)(want < 1 ? 1 : (want < cap ? want : cap));
-  const int32_t keep = lp.flow_keep < 0 ? 0 : (lp.flow_keep > kFlowRing - kFlowThreads ? kFlowRing - kFlowThreads : lp.flow_keep);
-  // no workgroup holds work while it waits, so the walk needs no co-residency
-  k_flow<<<grid, kFlowThreads, 0, s>>>(g, lc, fs, fb, lp.long_body < 1 ? 1 : lp.long_body, keep);
-  return hipGetLastError();
+  if (lp.flow_group == 512) return launch_flow_kernel<512>(g, lc, fs, fb, lp.flow_keep * 512 / 1024, device, s);
+  return launch_flow_kernel<1024>(g, lc, fs, fb, lp.flow_keep, device, s);
 }
 
 }  // namespace gt

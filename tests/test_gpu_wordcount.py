@@ -202,21 +202,21 @@ def test_vocabulary_beyond_bucket_table(ctx):
     check_wc_sort(ctx, g, expect_tokens=3000)
 
 
-@pytest.mark.parametrize("keep,long_body", [(0, 32), (64, 1), (4096, 8), (7168, 1 << 20)])
-def test_dataflow_walk_shapes(ctx, keep, long_body):
+@pytest.mark.parametrize("keep,group", [(0, 1024), (64, 512), (4096, 1024), (7168, 512), (1024, 512)])
+def test_dataflow_walk_shapes(ctx, keep, group):
     """The dataflow walk with rings that share everything beyond 0 or 64
-    rules (many published chunks), bodies walked by waves from 1 symbol or
-    never: the same counts as the oracle on recipe-scaled corpora and random
-    ones."""
+    rules (many published chunks) or keep up to 7168, in workgroups of 512
+    or 1024 threads: the same counts as the oracle on recipe-scaled corpora
+    and random ones."""
     import paper_2106_06889_amd as gt
     cases = [synth.workload("wc-100m", scale=0.02), synth.workload("seq-20m", scale=0.02),
              synth.workload("tv-4000files", scale=0.005)]
     for seed in (6, 7):
         c = synth.random_corpus(seed, 2, 5000, [40, 900][seed % 2])
         cases.append((c, synth.compress(c.tokens, c.file_off, c.vocab)))
-    old = ctx.get_param(gt.PARAM_FLOW_KEEP), ctx.get_param(gt.PARAM_LEVEL_LONG_BODY)
+    old = ctx.get_param(gt.PARAM_FLOW_KEEP), ctx.get_param(gt.PARAM_FLOW_GROUP)
     ctx.set_param(gt.PARAM_FLOW_KEEP, keep)
-    ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, long_body)
+    ctx.set_param(gt.PARAM_FLOW_GROUP, group)
     try:
         for c, g in cases:
             G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
@@ -227,7 +227,7 @@ def test_dataflow_walk_shapes(ctx, keep, long_body):
                 G.free()
     finally:
         ctx.set_param(gt.PARAM_FLOW_KEEP, old[0])
-        ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, old[1])
+        ctx.set_param(gt.PARAM_FLOW_GROUP, old[1])
 
 
 def test_dataflow_ring_overflow(ctx):
@@ -245,13 +245,13 @@ def test_dataflow_ring_overflow(ctx):
     rule_off = np.cumsum([0] + [len(b) for b in bodies]).astype(np.int64)
     g = synth.Grammar(rule_off, np.concatenate(bodies), np.array([0, 4], np.int64), V)
     assert oracle.check_structure(g) == 0
-    for long_body in (32, 1 << 20):  # walked by a wave, or by one thread
-        old = ctx.get_param(gt.PARAM_LEVEL_LONG_BODY)
-        ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, long_body)
+    for group in (512, 1024):
+        old = ctx.get_param(gt.PARAM_FLOW_GROUP)
+        ctx.set_param(gt.PARAM_FLOW_GROUP, group)
         try:
             check_wc_sort(ctx, g)
         finally:
-            ctx.set_param(gt.PARAM_LEVEL_LONG_BODY, old)
+            ctx.set_param(gt.PARAM_FLOW_GROUP, old)
 
 
 def test_deep_chain(ctx):
