@@ -516,18 +516,26 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   d.tile_rule = tile_rule;
 
   auto* pc = reinterpret_cast<gt::LoadCounters*>(ctx->pinned);
-  // phase 1: offsets and file spans (must hold before any kernel indexes by them)
-  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
-      !hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
-      !hip_ok(gt::launch_check_files(d.file_off, F, d.rule_off, lc, s), "check_files") ||
-      !hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read status") ||
-      !hip_ok(hipStreamSynchronize(s), "sync"))
-    return bail(GTADOC_ERR_HIP);
-  if (pc->status)
+  auto bad_layout = [&]() {
     return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s%s",
                      (pc->status & gt::ST_BAD_OFFSETS) ? "rule offsets not monotone in [0, S]; " : "",
                      (pc->status & gt::ST_EMPTY_BODY) ? "empty non-root rule body; " : "",
                      (pc->status & gt::ST_BAD_FILES) ? "file spans do not tile the root body" : ""));
+  };
+  // phase 1: offsets and file spans. The level walk's load reads them back
+  // first (its scratch is sized by the root's length); the dataflow load
+  // queues everything at once, and its passes that index by offsets leave
+  // at once on a bad layout, which the final read-back then reports.
+  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
+      !hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
+      !hip_ok(gt::launch_check_files(d.file_off, F, d.rule_off, lc, s), "check_files"))
+    return bail(GTADOC_ERR_HIP);
+  if (want_levels) {
+    if (!hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read status") ||
+        !hip_ok(hipStreamSynchronize(s), "sync"))
+      return bail(GTADOC_ERR_HIP);
+    if (pc->status) return bad_layout();
+  }
   // scratch of the level walk's bucketed mode (wide levels); without room
   // for it every level takes the atomic mode
   gt::WideBufs wide{};
@@ -576,6 +584,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
                        "read levels")) ||
       !hip_ok(hipStreamSynchronize(s), "sync"))
     return bail(GTADOC_ERR_HIP);
+  if (pc->status & gt::kBadLayout) return bad_layout();
   if (pc->status & (gt::ST_BAD_WORD | gt::ST_BAD_REF))
     return bail(fail(GTADOC_ERR_BAD_GRAMMAR, "bad grammar: %s%s",
                      (pc->status & gt::ST_BAD_WORD) ? "word id >= vocab; " : "",

@@ -66,6 +66,10 @@ enum : uint32_t {
   ST_PACK = 32u,         // a weight >= 2^40 or an in-degree >= 2^24 (beyond the packed load word)
   ST_FLOW = 64u,         // the dataflow walk ran out of queue room or waited past its bound (internal)
 };
+// A load may queue its later passes before the host has read the layout
+// checks; these passes then leave at once when one of these bits is set
+// (the offsets cannot be trusted for indexing).
+constexpr uint32_t kBadLayout = ST_BAD_OFFSETS | ST_EMPTY_BODY | ST_BAD_FILES;
 
 // Device view of a loaded grammar and its initialization-phase products.
 struct DevGrammar {

@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
   constexpr uint32_t kRing = FlowLds<kT>::kRing;
   __shared__ FlowLds<kT> L;
   uint32_t* status = &lc->status;
+  if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
   const int t = threadIdx.x;
   if (t == 0) {
     L.head = 0, L.tail = 0, L.pushed = 0, L.sp_n = 0, L.gleft = 0, L.gpos = 0, L.ticket = -1;

@@ -114,6 +114,7 @@ __device__ __forceinline__ void load4(const DevGrammar& g, const Tile& t, int32_
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, LoadCounters* lc) {
+  if (__hip_atomic_load(&lc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
   extern __shared__ int32_t lds_scan[];
   int32_t* roff = lds_scan;
   uint32_t* whist = reinterpret_cast<uint32_t*>(lds_scan + kTileRuleSlots);
@@ -186,7 +187,8 @@ hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_
 
 // In-degree scatter: one uint16 entry per rule reference into the bucket of
 // its child, at the block's cursor (offsets from the scan above).
-__global__ __launch_bounds__(kScanThreads) void k_ref_scatter(DevGrammar g, uint16_t* entries) {
+__global__ __launch_bounds__(kScanThreads) void k_ref_scatter(DevGrammar g, uint16_t* entries, const LoadCounters* lc) {
+  if (__hip_atomic_load(&lc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
   extern __shared__ int32_t lds_ref[];
   int32_t* roff = lds_ref;
   uint32_t* cursor = reinterpret_cast<uint32_t*>(lds_ref + kTileRuleSlots);
@@ -289,7 +291,7 @@ hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64
   if (e0 != hipSuccess) return e0;
   if (g.ntiles > 0) {
     const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.rc_nb);
-    k_ref_scatter<<<(unsigned)g.nblk, kScanThreads, shmem, s>>>(g, entries);
+    k_ref_scatter<<<(unsigned)g.nblk, kScanThreads, shmem, s>>>(g, entries, lc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
