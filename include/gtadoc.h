@@ -192,8 +192,9 @@ int gtadoc_decompress(gtadoc_grammar g, int32_t* tokens, int64_t* file_off, void
  * nonzero count, ordered by count descending, then word id ascending.
  * `word_counts` is a device array of vocab uint64 from gtadoc_word_count on
  * the same grammar, or NULL to compute it inside the call. Writes ids[0..K)
- * and counts[0..K) (caller-owned device arrays with room for vocab entries)
- * and K to the device int64 *num. Asynchronous. Errors: INVALID_ARG, OOM, HIP. */
+ * and counts[0..K) (caller-owned device arrays with room for vocab entries;
+ * entries K..vocab are scratch on return) and K to the device int64 *num.
+ * Asynchronous. Errors: INVALID_ARG, OOM, HIP. */
 int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, uint64_t* counts, int64_t* num,
                 void* stream);
 

@@ -402,13 +402,16 @@ bool hip_ok(hipError_t e, const char* what) {
 // word totals (lc), the word-bucket offsets (d.wc_off), the reference-bucket
 // offsets (d.rc_off, scratch), then one packed word per rule in d.w
 // (frequency in the root << kPendBits | in-edges from other rules; the root
-// holds weight 1). Returns false with the error recorded.
+// holds weight 1). With `zeroed`, the offset histograms are zero already.
+// Returns false with the error recorded.
 bool run_degrees(Call& call, gt::DevGrammar& d, gt::LoadCounters* lc, uint32_t* sums, int64_t n_wc_off,
-                 int64_t n_rc_off, hipStream_t s) {
+                 int64_t n_rc_off, hipStream_t s, bool zeroed = false) {
   const bool atomic_degrees = d.rc_nb == 0;
   if ((atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, d.R, 0, s), "fill")) ||
-      (n_wc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
-      (n_rc_off && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
+      (!zeroed && n_wc_off &&
+       !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.wc_off), n_wc_off, 0, s), "fill")) ||
+      (!zeroed && n_rc_off &&
+       !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
       !hip_ok(gt::launch_scan_symbols(d, lc, s), "scan_symbols") ||
       (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
       (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
@@ -526,11 +529,19 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   // first (its scratch is sized by the root's length); the dataflow load
   // queues everything at once, and its passes that index by offsets leave
   // at once on a bad layout, which the final read-back then reports.
-  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill") ||
-      !hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
-      !hip_ok(gt::launch_check_files(d.file_off, F, d.rule_off, lc, s), "check_files"))
+  if (!hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(lc), sizeof(gt::LoadCounters) / 4, 0, s), "fill"))
     return bail(GTADOC_ERR_HIP);
-  if (want_levels) {
+  if (!want_levels) {
+    // the checks, the histograms' zeros and the walk's counters in one launch
+    if (!hip_ok(gt::launch_load_prologue(d.rule_off, R, S, d.file_off, F, tile_rule, d.ntiles, lc, d.wc_off, n_wc_off,
+                                         d.rc_off, n_rc_off, reinterpret_cast<uint32_t*>(fs),
+                                         sizeof(gt::FlowState) / 4, s),
+                "checks"))
+      return bail(GTADOC_ERR_HIP);
+  } else {
+    if (!hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||
+        !hip_ok(gt::launch_check_files(d.file_off, F, d.rule_off, lc, s), "check_files"))
+      return bail(GTADOC_ERR_HIP);
     if (!hip_ok(hipMemcpyAsync(pc, lc, sizeof(gt::LoadCounters), hipMemcpyDeviceToHost, s), "read status") ||
         !hip_ok(hipStreamSynchronize(s), "sync"))
       return bail(GTADOC_ERR_HIP);
@@ -559,11 +570,9 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   // phase 2: symbols, in-degrees, then the weight walk: the level walk
   // (levels and weights) or the dataflow walk (weights; levels on first need)
   PhaseScope t_load(ctx, GTADOC_PHASE_LOAD, s);
-  if ((want_levels && !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill")) ||
-      (!want_levels && !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(fs), sizeof(gt::FlowState) / 4, 0, s), "fill")))
-    return bail(GTADOC_ERR_HIP);
-  if (!run_degrees(call, d, lc, sums, n_wc_off, n_rc_off, s)) return bail(GTADOC_ERR_HIP);
-  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s, want_levels ? nullptr : flow.qw), "levels"))
+  if (want_levels && !hip_ok(gt::launch_fill_i32(level_cnt, R + 2, 0, s), "fill")) return bail(GTADOC_ERR_HIP);
+  if (!run_degrees(call, d, lc, sums, n_wc_off, n_rc_off, s, /*zeroed=*/!want_levels)) return bail(GTADOC_ERR_HIP);
+  if (!hip_ok(gt::launch_level_frontier(d, lc, sums, s, want_levels ? nullptr : flow.qw, fs), "levels"))
     return bail(GTADOC_ERR_HIP);
   if (want_levels && !hip_ok(gt::prepare_level_walk(d, lc, sums, wide, s), "levels"))
     return bail(GTADOC_ERR_HIP);
@@ -828,13 +837,11 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
   sc.key[1] = call.scratch<uint64_t>(V);
   sc.val[0] = call.scratch<uint32_t>(V);
   sc.val[1] = call.scratch<uint32_t>(V);
-  sc.hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(V));
-  sc.num = call.scratch<int64_t>(1);
-  sc.capacity = V;
-  if (!sc.key[0] || !sc.key[1] || !sc.val[0] || !sc.val[1] || !sc.hist || !sc.num) return oom("sort scratch", 24ull * V);
-  const int key_bytes = std::max(1, (bitlen((uint64_t)g->st.tokens) + 7) / 8);
+  sc.hist = call.scratch<uint32_t>(gt::word_sort_hist_entries(V));
+  if (!sc.key[0] || !sc.key[1] || !sc.val[0] || !sc.val[1] || !sc.hist) return oom("sort scratch", 24ull * V);
+  const int key_bits = std::max(1, bitlen((uint64_t)g->st.tokens));  // no count exceeds the token total
   PhaseScope t_sort(g->ctx, GTADOC_PHASE_SORT, s);
-  HIP_TRY(gt::launch_sort_by_count(word_counts, V, key_bytes, sc, ids, counts, num, s));
+  HIP_TRY(gt::launch_sort_by_count(word_counts, V, key_bits, sc, ids, counts, num, s));
   t_sort.end();
   return GTADOC_OK;
 }

@@ -136,16 +136,23 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // load phase
 hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int32_t* tile_rule, int64_t ntiles,
                               LoadCounters* lc, hipStream_t s);
+// both checks plus the zero fills of wc_off, rc_off and `zero` in one launch
+// (lc zero before it)
+hipError_t launch_load_prologue(const int64_t* rule_off, int64_t R, int64_t S, const int64_t* file_off, int64_t F,
+                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, uint32_t* wc_off, int64_t n_wc,
+                                uint32_t* rc_off, int64_t n_rc, uint32_t* zero, int64_t n_zero, hipStream_t s);
 hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc,
                               hipStream_t s);
 hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_t s);
 // in-degrees and initial weights (packed in g.w) from the reference entries
 // (after the offsets are scanned)
 hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s);
+struct FlowState;
 // level 1 (rules no rule references) by compaction into g.level_rule (and,
-// when qw is given, their weights into qw), then the level walk
+// when qw is given, their weights into qw and the dataflow walk's counters
+// into fs), then the level walk
 hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s,
-                                 uint64_t* qw = nullptr);
+                                 uint64_t* qw = nullptr, FlowState* fs = nullptr);
 hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, const WideBufs& wide,
                               hipStream_t s);
 // Launch shape of the level walk (context parameters, tunable):
@@ -175,7 +182,7 @@ hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s);
 // Dataflow walk (weights without levels): the global queue of ready rules
 // (level 1 first, as compacted into level_rule with its weights in qw) and
 // the descriptors of the chunks published into it; counters in FlowState
-// (set up by the launcher from lc->frontier0).
+// (set up by the level-1 compaction).
 struct FlowState {
   int64_t live;       // rules queued anywhere or being walked
   int64_t n1;         // rules of level 1
@@ -184,6 +191,7 @@ struct FlowState {
   uint32_t nspill;    // chunks published beyond level 1
   uint32_t nchunks0;  // chunks of level 1
 };
+constexpr int kFlowChunk0 = 1024;  // rules per level-1 chunk of the dataflow walk's queue
 struct FlowBufs {
   int32_t* qc;     // [qcap] rules (level_rule)
   uint64_t* qw;    // [qcap] their final weights
@@ -222,11 +230,10 @@ int64_t scan_scratch_entries(int64_t n);
 struct SortScratch {
   uint64_t* key[2];
   uint32_t* val[2];
-  uint32_t* hist;       // [256 * nblocks]
-  int64_t* num;         // device K
-  int64_t capacity;
+  uint32_t* hist;       // [word_sort_hist_entries(V)]
 };
 int64_t sort_scratch_hist_entries(int64_t n);
+int64_t word_sort_hist_entries(int64_t V);
 
 // term vector / inverted index
 struct TvFiles {
@@ -317,7 +324,7 @@ hipError_t launch_occ_write(const uint64_t* table, int64_t cap, const uint32_t* 
                             hipStream_t s);
 hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
                                 uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s);
-hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,
+hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bits, SortScratch& sc, uint32_t* ids_out,
                                 uint64_t* cnt_out, int64_t* num_out, hipStream_t s);
 
 }  // namespace gt

@@ -51,7 +51,6 @@
 
 namespace gt {
 
-constexpr int kFlowChunk0 = 1024;  // rules per level-1 chunk
 constexpr uint32_t kFlowSpinLimit = 1u << 21;
 
 template <int kT>
@@ -228,7 +227,7 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
   constexpr uint32_t kRing = FlowLds<kT>::kRing;
   __shared__ FlowLds<kT> L;
   uint32_t* status = &lc->status;
-  if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
+  if (lc->status & kBadLayout) return;  // set before this launch
   const int t = threadIdx.x;
   if (t == 0) {
     L.head = 0, L.tail = 0, L.pushed = 0, L.sp_n = 0, L.gleft = 0, L.gpos = 0, L.ticket = -1;
@@ -366,17 +365,6 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
   }
 }
 
-__global__ void k_flow_init(const LoadCounters* lc, FlowState* fs) {
-  if (threadIdx.x != 0) return;
-  const int64_t n1 = lc->frontier0;
-  fs->n1 = n1;
-  fs->nchunks0 = (uint32_t)((n1 + kFlowChunk0 - 1) / kFlowChunk0);
-  fs->live = n1;
-  fs->space = (uint32_t)n1;
-  fs->ticket = 0;
-  fs->nspill = 0;
-}
-
 template <int kT>
 hipError_t launch_flow_kernel(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb, int32_t keep,
                               int device, hipStream_t s) {
@@ -395,10 +383,7 @@ hipError_t launch_flow_kernel(const DevGrammar& g, LoadCounters* lc, FlowState* 
 
 hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb,
                             const LevelParams& lp, int device, hipStream_t s) {
-  hipError_t e = launch_fill_u64(fb.desc, fb.ndesc, 0, s);
-  if (e != hipSuccess) return e;
-  k_flow_init<<<1, 64, 0, s>>>(lc, fs);
-  e = hipGetLastError();
+  const hipError_t e = launch_fill_u64(fb.desc, fb.ndesc, 0, s);
   if (e != hipSuccess) return e;
   if (lp.flow_group == 512) return launch_flow_kernel<512>(g, lc, fs, fb, lp.flow_keep * 512 / 1024, device, s);
   return launch_flow_kernel<1024>(g, lc, fs, fb, lp.flow_keep, device, s);

@@ -44,7 +44,17 @@ __global__ __launch_bounds__(256) void k_zero_count(const uint64_t* pw, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t R, const uint32_t* off,
-                                                    int32_t* out, uint64_t* qw) {
+                                                    int32_t* out, uint64_t* qw, FlowState* fs, const int64_t* n1p) {
+  if (fs && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the dataflow walk's queue starts with level 1 in chunks of kFlowChunk0
+    const int64_t n1 = *n1p;
+    fs->n1 = n1;
+    fs->nchunks0 = (uint32_t)((n1 + kFlowChunk0 - 1) / kFlowChunk0);
+    fs->live = n1;
+    fs->space = (uint32_t)n1;
+    fs->ticket = 0;
+    fs->nspill = 0;
+  }
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
   uint32_t c = 0;
   bool z[16];
@@ -503,7 +513,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_levels(DevGrammar g, int32_t*
 }
 
 hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s,
-                                 uint64_t* qw) {
+                                 uint64_t* qw, FlowState* fs) {
   // level 1 by compaction (scratch: per-block counts, then the scan's block sums)
   const int64_t nb = (g.R + kRadixTile - 1) / kRadixTile;
   k_zero_count<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch);
@@ -511,7 +521,7 @@ hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t
   if (e != hipSuccess) return e;
   e = launch_scan_u32(scratch, nb, &lc->frontier0, scratch + nb, s);
   if (e != hipSuccess) return e;
-  k_zero_write<<<(unsigned)nb, 256, 0, s>>>(g.w, g.R, scratch, g.level_rule, qw);
+  k_zero_write<<<(unsigned)(nb > 0 ? nb : 1), 256, 0, s>>>(g.w, g.R, scratch, g.level_rule, qw, fs, &lc->frontier0);
   return hipGetLastError();
 }
 

@@ -75,6 +75,59 @@ hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int
   return hipGetLastError();
 }
 
+// The same checks in one launch, with the zero fills of the load's
+// histograms and the dataflow walk's counters (one launch instead of six
+// keeps the GPU from waiting for the host at the start of a load): rule
+// offsets and the tile table (k_check_rules, k_root_tiles), file spans
+// (k_check_files), and zeros over wc_off, rc_off and `zero`. lc must be
+// zero before the launch.
+__global__ __launch_bounds__(256) void k_load_prologue(const int64_t* rule_off, int64_t R, int64_t S,
+                                                       const int64_t* file_off, int64_t F, int32_t* tile_rule,
+                                                       int64_t ntiles, LoadCounters* lc, uint32_t* wc_off,
+                                                       int64_t n_wc, uint32_t* rc_off, int64_t n_rc, uint32_t* zero,
+                                                       int64_t n_zero) {
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  for (int64_t r = tid; r < R; r += nth) {
+    const int64_t lo = rule_off[r], hi = rule_off[r + 1];
+    uint32_t b = 0;
+    if (lo < 0 || hi > S || lo > hi) b |= ST_BAD_OFFSETS;
+    if (r == 0 && lo != 0) b |= ST_BAD_OFFSETS;
+    if (r == R - 1 && hi != S) b |= ST_BAD_OFFSETS;
+    if (r > 0 && hi == lo) b |= ST_EMPTY_BODY;
+    bad |= b;
+    if (b) continue;
+    if (r == 0) {
+      lc->root_syms = hi;
+      continue;
+    }
+    for (int64_t k = (lo + kTileSyms - 1) / kTileSyms; k * kTileSyms < hi; ++k) tile_rule[k] = (int32_t)r;
+  }
+  const int64_t root_end = rule_off[1];
+  for (int64_t k = tid; k < ntiles; k += nth)
+    if (k * kTileSyms < root_end) tile_rule[k] = 0;
+  if (tid == 0) tile_rule[ntiles] = (int32_t)(R - 1);
+  for (int64_t f = tid; f < F; f += nth) {
+    const int64_t a = file_off[f], b = file_off[f + 1];
+    if (a > b || (f == 0 && a != 0) || (f == F - 1 && b != root_end)) bad |= ST_BAD_FILES;
+  }
+  for (int64_t i = tid; i < n_wc; i += nth) wc_off[i] = 0;
+  for (int64_t i = tid; i < n_rc; i += nth) rc_off[i] = 0;
+  for (int64_t i = tid; i < n_zero; i += nth) zero[i] = 0;
+  if (bad) atomicOr(&lc->status, bad);
+}
+
+hipError_t launch_load_prologue(const int64_t* rule_off, int64_t R, int64_t S, const int64_t* file_off, int64_t F,
+                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, uint32_t* wc_off, int64_t n_wc,
+                                uint32_t* rc_off, int64_t n_rc, uint32_t* zero, int64_t n_zero, hipStream_t s) {
+  int64_t n = R > ntiles ? R : ntiles;
+  if (F > n) n = F;
+  k_load_prologue<<<fill_blocks(n), 256, 0, s>>>(rule_off, R, S, file_off, F, tile_rule, ntiles, lc, wc_off, n_wc,
+                                                 rc_off, n_rc, zero, n_zero);
+  return hipGetLastError();
+}
+
 // File spans tile the root body: file_off[0] = 0, non-decreasing,
 // file_off[F] = length of the root body.
 __global__ void k_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc) {
@@ -114,7 +167,10 @@ __device__ __forceinline__ void load4(const DevGrammar& g, const Tile& t, int32_
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_symbols(DevGrammar g, LoadCounters* lc) {
-  if (__hip_atomic_load(&lc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
+  // a plain load: the layout bits were set by earlier kernels, and a
+  // device-scope load would queue behind the other blocks' counter atomics
+  // on this line
+  if (lc->status & kBadLayout) return;
   extern __shared__ int32_t lds_scan[];
   int32_t* roff = lds_scan;
   uint32_t* whist = reinterpret_cast<uint32_t*>(lds_scan + kTileRuleSlots);
@@ -188,7 +244,7 @@ hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_
 // In-degree scatter: one uint16 entry per rule reference into the bucket of
 // its child, at the block's cursor (offsets from the scan above).
 __global__ __launch_bounds__(kScanThreads) void k_ref_scatter(DevGrammar g, uint16_t* entries, const LoadCounters* lc) {
-  if (__hip_atomic_load(&lc->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadLayout) return;
+  if (lc->status & kBadLayout) return;
   extern __shared__ int32_t lds_ref[];
   int32_t* roff = lds_ref;
   uint32_t* cursor = reinterpret_cast<uint32_t*>(lds_ref + kTileRuleSlots);

@@ -2,70 +2,217 @@
 // then word id ascending (an application the paper keeps from CompressDirect,
 // Section "Implementation").
 //
-// Stable compaction of the nonzero counts (ids stay ascending), then a
-// stable least-significant-digit radix sort on the count with 8-bit digits,
-// only over the bytes that the largest possible count (the token total)
-// needs. Ranks inside a tile come from wave64 ballots over the digit bits,
-// so equal digits keep their input order and ties stay in id order.
+// A stable least-significant-digit radix sort of all V (count, id) pairs on
+// the count, over the bits that the largest possible count (the token total)
+// needs, in as few passes of at most 9-bit digits as cover them (3 passes
+// for 27 bits). The first pass reads the counts directly (ids are the
+// positions, so ties start in id order) and counts the zeros; zero counts
+// sort last, and K = V - zeros. A pass is three launches: per-tile digit
+// histograms (digit-major), a scan of each digit's column over the tiles
+// (one workgroup per digit, which also leaves the digit's total), and the
+// stable scatter, which turns the digit totals into digit starts itself.
+// Tiles are 4096 keys (1024 threads x 4); within a tile every wave owns 256
+// consecutive keys, ranks equal digits by ballots over the digit bits and
+// keeps running counts per digit in LDS, and waves are ordered by a prefix
+// over their counts.
 #include "device.h"
 #include "radix.h"
 
 namespace gt {
 
-// Nonzero counts per 4096-id block.
-__global__ __launch_bounds__(256) void k_nz_count(const uint64_t* counts, int32_t V, uint32_t* blk_cnt) {
-  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (i0 + k < V && counts[i0 + k] != 0) ++c;
-  __shared__ uint32_t lds[4];
-  uint32_t total;
-  block_exclusive_scan_256(c, lds, &total);
-  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = total;
+constexpr int kWsThreads = 1024;
+constexpr int kWsPer = 4;
+constexpr int kWsTile = kWsThreads * kWsPer;
+constexpr int kWsWaves = kWsThreads / 64;
+constexpr int kWsMaxBits = 9;
+constexpr int kWsMaxDigits = 1 << kWsMaxBits;
+constexpr int kWsColThreads = 256;
+
+// Digit of a count for a descending sort over the low `bits` bits.
+__device__ __forceinline__ uint32_t ws_digit(uint64_t count, int shift, int dbits) {
+  return (uint32_t)((~count >> shift) & ((1u << dbits) - 1u));
 }
 
-// Write (count, id) of the nonzero entries at their compacted positions.
-__global__ __launch_bounds__(256) void k_nz_write(const uint64_t* counts, int32_t V, const uint32_t* blk_off,
-                                                  uint64_t* key, uint32_t* val) {
-  const int64_t i0 = blockIdx.x * (int64_t)kRadixTile + threadIdx.x * 16;
-  uint64_t c[16];
-  uint32_t n = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    c[k] = (i0 + k < V) ? counts[i0 + k] : 0;
-    n += c[k] != 0;
+// Lanes of the wave whose digit equals this lane's (among `valid` lanes).
+__device__ __forceinline__ uint64_t ws_peers(bool valid, uint32_t d, int dbits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < dbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
   }
-  __shared__ uint32_t lds[4];
-  uint32_t total;
-  uint32_t pos = blk_off[blockIdx.x] + block_exclusive_scan_256(n, lds, &total);
+  return peers;
+}
+
+// Digit histogram of every tile: hist[d * nb + tile]. The first pass reads
+// the counts and also writes the tile's number of zero counts.
+template <bool kFirst>
+__global__ __launch_bounds__(kWsThreads) void k_ws_hist(const uint64_t* keys, int64_t V, int shift, int dbits,
+                                                        uint32_t* hist, int nb, uint32_t* zeros) {
+  __shared__ uint32_t h[kWsMaxDigits];
+  __shared__ uint32_t zs[kWsWaves];
+  const int nd = 1 << dbits;
+  for (int d = threadIdx.x; d < nd; d += kWsThreads) h[d] = 0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t base = (int64_t)blockIdx.x * kWsTile + (int64_t)wave * (kWsPer * 64);
+  uint32_t z = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k)
-    if (c[k] != 0) {
-      key[pos] = c[k];
-      val[pos] = (uint32_t)(i0 + k);
-      ++pos;
+  for (int j = 0; j < kWsPer; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < V;
+    const uint64_t k = valid ? keys[idx] : 0;
+    if (kFirst) z += valid && k == 0;
+    const uint32_t d = ws_digit(k, shift, dbits);
+    const uint64_t peers = ws_peers(valid, d, dbits);
+    // one LDS add per distinct digit of the step (Zipf-hot digits would
+    // otherwise serialize on one address)
+    if (valid && (peers & lanes_below()) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+  }
+  if (kFirst) {
+    for (int o = 32; o >= 1; o >>= 1) z += __shfl_xor(z, o);
+    if (lane == 0) zs[wave] = z;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < nd; d += kWsThreads) hist[(int64_t)d * nb + blockIdx.x] = h[d];
+  if (kFirst && threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kWsWaves; ++w) t += zs[w];
+    zeros[blockIdx.x] = t;
+  }
+}
+
+// Column scan: workgroup d scans hist[d * nb .. d * nb + nb) (exclusive, in
+// place) and writes the digit's total to tot[d]. With `zeros`, workgroup 0
+// also writes *num = V - (zero counts over the tiles).
+__global__ __launch_bounds__(kWsColThreads) void k_ws_colscan(uint32_t* hist, int nb, uint32_t* tot,
+                                                              const uint32_t* zeros, int64_t V, int64_t* num) {
+  __shared__ uint32_t part[kWsColThreads / 64];
+  uint32_t* col = hist + (int64_t)blockIdx.x * nb;
+  uint32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += kWsColThreads) {
+    const int b = b0 + (int)threadIdx.x;
+    const uint32_t v = b < nb ? col[b] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan_256(v, part, &total);
+    if (b < nb) col[b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+  if (zeros && blockIdx.x == 0) {
+    uint32_t z = 0;
+    for (int b = threadIdx.x; b < nb; b += kWsColThreads) z += zeros[b];
+    uint32_t total;
+    block_exclusive_scan_256(z, part, &total);
+    if (threadIdx.x == 0) *num = V - (int64_t)total;
+  }
+}
+
+// Stable scatter of one pass. The first pass takes the counts as keys and
+// the positions as values.
+template <bool kFirst>
+__global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                           uint32_t* vout, int64_t V, int shift, int dbits,
+                                                           const uint32_t* hist, const uint32_t* tot, int nb) {
+  __shared__ uint32_t wcnt[kWsWaves][kWsMaxDigits];
+  __shared__ uint32_t base[kWsWaves][kWsMaxDigits];
+  __shared__ uint32_t dstart[kWsMaxDigits];
+  __shared__ uint32_t part[kWsWaves];
+  const int nd = 1 << dbits;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  // digit starts: exclusive scan of the digit totals (nd <= 512 <= threads)
+  {
+    const uint32_t v = (int)threadIdx.x < nd ? tot[threadIdx.x] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
     }
+    if (lane == 63) part[wave] = x;
+    for (int d = lane; d < nd; d += 64) wcnt[wave][d] = 0;
+    __syncthreads();
+    uint32_t off = x - v;
+    for (int w = 0; w < wave; ++w) off += part[w];
+    if ((int)threadIdx.x < nd) dstart[threadIdx.x] = off;
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * kWsTile + (int64_t)wave * (kWsPer * 64);
+  uint64_t key[kWsPer];
+  uint32_t val[kWsPer], rank[kWsPer], dig[kWsPer];
+#pragma unroll
+  for (int j = 0; j < kWsPer; ++j) {
+    const int64_t idx = t0 + j * 64 + lane;
+    const bool valid = idx < V;
+    const uint64_t k = valid ? kin[idx] : 0;
+    const uint32_t d = ws_digit(k, shift, dbits);
+    const uint64_t peers = ws_peers(valid, d, dbits);
+    const uint32_t before = wcnt[wave][d];
+    const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+    __builtin_amdgcn_wave_barrier();
+    if (valid && r == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    key[j] = k;
+    val[j] = valid ? (kFirst ? (uint32_t)idx : vin[idx]) : 0u;
+    rank[j] = valid ? before + r : 0xffffffffu;
+    dig[j] = d;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < nd; d += kWsThreads) {
+    uint32_t acc = dstart[d] + hist[(int64_t)d * nb + blockIdx.x];
+    for (int w = 0; w < kWsWaves; ++w) {
+      base[w][d] = acc;
+      acc += wcnt[w][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kWsPer; ++j) {
+    if (rank[j] == 0xffffffffu) continue;
+    const uint32_t pos = base[wave][dig[j]] + rank[j];
+    kout[pos] = key[j];
+    vout[pos] = val[j];
+  }
 }
 
 int64_t sort_scratch_hist_entries(int64_t n) { return radix_hist_entries(n); }
 
-hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bytes, SortScratch& sc, uint32_t* ids_out,
+int64_t word_sort_hist_entries(int64_t V) {
+  const int64_t nb = (V + kWsTile - 1) / kWsTile;
+  return (int64_t)kWsMaxDigits * (nb > 0 ? nb : 1) + (nb > 0 ? nb : 1) + kWsMaxDigits;
+}
+
+hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bits, SortScratch& sc, uint32_t* ids_out,
                                 uint64_t* cnt_out, int64_t* num_out, hipStream_t s) {
-  const int nb = (int)((V + kRadixTile - 1) / kRadixTile);
-  uint32_t* blk = sc.hist;  // reused: block counts, then digit histograms
-  k_nz_count<<<nb, 256, 0, s>>>(counts, V, blk);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = launch_scan_u32(blk, nb, sc.num, blk + nb, s);  // exclusive offsets; total K -> *sc.num
-  if (e != hipSuccess) return e;
-  k_nz_write<<<nb, 256, 0, s>>>(counts, V, blk, sc.key[0], sc.val[0]);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = radix_sort_pairs<uint32_t>(sc.key[0], sc.val[0], sc.key[1], sc.val[1], sc.num, V, 0, 8 * key_bytes,
-                                 /*descending=*/true, sc.hist, cnt_out, ids_out, s);
-  if (e != hipSuccess) return e;
-  return hipMemcpyAsync(num_out, sc.num, sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+  const int nb = (int)((V + kWsTile - 1) / kWsTile);
+  if (nb == 0) return launch_fill_i32(reinterpret_cast<int32_t*>(num_out), 2, 0, s);
+  const int bits = key_bits < 1 ? 1 : (key_bits > 64 ? 64 : key_bits);
+  const int npass = (bits + kWsMaxBits - 1) / kWsMaxBits;
+  const int dbits = (bits + npass - 1) / npass;
+  uint32_t* hist = sc.hist;
+  uint32_t* zeros = sc.hist + (int64_t)kWsMaxDigits * nb;
+  uint32_t* tot = zeros + nb;
+  const uint64_t* kin = counts;
+  const uint32_t* vin = nullptr;
+  for (int p = 0; p < npass; ++p) {
+    const int shift = p * dbits;
+    const bool last = p == npass - 1;
+    uint64_t* kdst = last ? cnt_out : sc.key[p & 1];
+    uint32_t* vdst = last ? ids_out : sc.val[p & 1];
+    if (p == 0) k_ws_hist<true><<<nb, kWsThreads, 0, s>>>(kin, V, shift, dbits, hist, nb, zeros);
+    else k_ws_hist<false><<<nb, kWsThreads, 0, s>>>(kin, V, shift, dbits, hist, nb, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ws_colscan<<<1 << dbits, kWsColThreads, 0, s>>>(hist, nb, tot, p == 0 ? zeros : nullptr, V, num_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (p == 0) k_ws_scatter<true><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, shift, dbits, hist, tot, nb);
+    else k_ws_scatter<false><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, shift, dbits, hist, tot, nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    kin = kdst;
+    vin = vdst;
+  }
+  return hipSuccess;
 }
 
 }  // namespace gt
