@@ -406,6 +406,8 @@ bool hip_ok(hipError_t e, const char* what) {
 // Returns false with the error recorded.
 bool run_degrees(Call& call, gt::DevGrammar& d, gt::LoadCounters* lc, uint32_t* sums, int64_t n_wc_off,
                  int64_t n_rc_off, hipStream_t s, bool zeroed = false) {
+  // with `zeroed`, the packed words are zero too when the in-degrees are
+  // reduced by bucket
   const bool atomic_degrees = d.rc_nb == 0;
   if ((atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, d.R, 0, s), "fill")) ||
       (!zeroed && n_wc_off &&
@@ -424,7 +426,7 @@ bool run_degrees(Call& call, gt::DevGrammar& d, gt::LoadCounters* lc, uint32_t* 
       oom("reference entries", 2 * (uint64_t)d.S);
       return false;
     }
-    if (!hip_ok(gt::launch_in_degrees(d, ref_entries, &lc->rc_entries, lc, s), "in_degrees")) return false;
+    if (!hip_ok(gt::launch_in_degrees(d, ref_entries, &lc->rc_entries, lc, s, zeroed), "in_degrees")) return false;
   }
   return true;
 }
@@ -533,10 +535,13 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
     return bail(GTADOC_ERR_HIP);
   if (!want_levels) {
     // the checks, the histograms' zeros and the walk's counters in one launch
-    if (!hip_ok(gt::launch_load_prologue(d.rule_off, R, S, d.file_off, F, tile_rule, d.ntiles, lc, d.wc_off, n_wc_off,
-                                         d.rc_off, n_rc_off, reinterpret_cast<uint32_t*>(fs),
-                                         sizeof(gt::FlowState) / 4, s),
-                "checks"))
+    gt::ZeroRanges z{};
+    z.add(d.wc_off, n_wc_off);
+    z.add(d.rc_off, n_rc_off);
+    z.add(fs, sizeof(gt::FlowState) / 4);
+    z.add(flow.desc, 2 * (int64_t)flow.ndesc);
+    if (d.rc_nb) z.add(d.w, 2 * R);  // the packed words the in-degree reduce adds into
+    if (!hip_ok(gt::launch_load_prologue(d.rule_off, R, S, d.file_off, F, tile_rule, d.ntiles, lc, z, s), "checks"))
       return bail(GTADOC_ERR_HIP);
   } else {
     if (!hip_ok(gt::launch_check_rules(d.rule_off, R, S, tile_rule, d.ntiles, lc, s), "check_rules") ||

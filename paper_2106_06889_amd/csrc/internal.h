@@ -136,21 +136,30 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // load phase
 hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int32_t* tile_rule, int64_t ntiles,
                               LoadCounters* lc, hipStream_t s);
-// both checks plus the zero fills of wc_off, rc_off and `zero` in one launch
-// (lc zero before it)
+// both checks plus zero fills of up to 6 ranges (in 32-bit words) in one
+// launch (lc zero before it)
+struct ZeroRanges {
+  uint32_t* p[6];
+  int64_t n[6];
+  int count;
+  void add(void* ptr, int64_t words) {
+    if (ptr && words > 0) p[count] = static_cast<uint32_t*>(ptr), n[count] = words, ++count;
+  }
+};
 hipError_t launch_load_prologue(const int64_t* rule_off, int64_t R, int64_t S, const int64_t* file_off, int64_t F,
-                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, uint32_t* wc_off, int64_t n_wc,
-                                uint32_t* rc_off, int64_t n_rc, uint32_t* zero, int64_t n_zero, hipStream_t s);
+                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, const ZeroRanges& z,
+                                hipStream_t s);
 hipError_t launch_check_files(const int64_t* file_off, int64_t F, const int64_t* rule_off, LoadCounters* lc,
                               hipStream_t s);
 hipError_t launch_scan_symbols(const DevGrammar& g, LoadCounters* lc, hipStream_t s);
 // in-degrees and initial weights (packed in g.w) from the reference entries
 // (after the offsets are scanned)
-hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s);
+hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s,
+                             bool w_zeroed = false);
 struct FlowState;
-// level 1 (rules no rule references) by compaction into g.level_rule (and,
-// when qw is given, their weights into qw and the dataflow walk's counters
-// into fs), then the level walk
+// level 1 (rules no rule references) by compaction into g.level_rule in
+// rule-id order (and, when qw is given, their weights into qw and the
+// dataflow walk's counters into fs), then the level walk
 hipError_t launch_level_frontier(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, hipStream_t s,
                                  uint64_t* qw = nullptr, FlowState* fs = nullptr);
 hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* scratch, const WideBufs& wide,
@@ -180,16 +189,15 @@ hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounte
 hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s);
 
 // Dataflow walk (weights without levels): the global queue of ready rules
-// (level 1 first, as compacted into level_rule with its weights in qw) and
-// the descriptors of the chunks published into it; counters in FlowState
-// (set up by the level-1 compaction).
+// (level 1 first, with their weights) and the descriptors of the chunks
+// published into it; counters in FlowState.
 struct FlowState {
   int64_t live;       // rules queued anywhere or being walked
   int64_t n1;         // rules of level 1
   uint32_t space;     // queue entries reserved (level 1 first)
   uint32_t ticket;    // next chunk ticket
   uint32_t nspill;    // chunks published beyond level 1
-  uint32_t nchunks0;  // chunks of level 1
+  uint32_t idle;      // workgroups waiting for work
 };
 constexpr int kFlowChunk0 = 1024;  // rules per level-1 chunk of the dataflow walk's queue
 struct FlowBufs {
@@ -198,8 +206,10 @@ struct FlowBufs {
   uint64_t* desc;  // [ndesc] published chunks: start << 16 | count, 0 = not yet
   uint32_t qcap, ndesc;
 };
-// placed and tokens are added to lc (zero before); g.w holds packed words
-// on entry and unpacks like after the level walk
+// The walk, after launch_level_frontier has queued level 1. placed and
+// tokens are added to lc (zero before); fs (beyond what the frontier set)
+// and fb.desc must be zero; g.w holds packed words on entry and unpacks like
+// after the level walk.
 hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb,
                             const LevelParams& lp, int device, hipStream_t s);
 

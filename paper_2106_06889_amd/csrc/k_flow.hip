@@ -33,7 +33,8 @@
 // then from a held range of a global queue. The queue starts with level 1
 // (the rules without pending in-edges, in chunks of kFlowChunk0) and grows by
 // chunks that workgroups publish when their ring holds more than `keep`
-// rules, or when a round readies more rules than the ring holds. Tickets hand out the
+// rules (more than one round's worth while some workgroup waits idle), or
+// when a round readies more rules than the ring holds. Tickets hand out the
 // chunks in order: a workgroup takes the next one when its range is used up
 // and its ring holds less than a round, and keeps working from its ring
 // until a published chunk is there. A published chunk is a range of
@@ -144,6 +145,7 @@ __device__ __forceinline__ void flow_push(FlowLds<kT>& L, FlowState* fs, const F
 template <int kT>
 __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const FlowBufs& fb, uint32_t* status) {
   const uint32_t n0 = L.n0;
+  bool idle = false;
   for (uint32_t it = 0;; ++it) {
     if (L.gleft == 0) {
       if (L.ticket < 0 && L.tail - L.head < (uint32_t)kT) L.ticket = atomicAdd(&fs->ticket, 1u);
@@ -166,6 +168,10 @@ __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const
       }
     }
     if (L.tail != L.head || L.gleft) break;
+    if (!idle) {  // counted idle while it waits, so that busy workgroups share
+      idle = true;
+      atomicAdd(&fs->idle, 1u);
+    }
     // zero only once every rule has been walked: the chunk will never come
     if (__hip_atomic_load(&fs->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       L.n = -1;
@@ -178,6 +184,7 @@ __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  if (idle) atomicSub(&fs->idle, 1u);
   const uint32_t occ = L.tail - L.head;
   const uint32_t nr = occ < (uint32_t)kT ? occ : (uint32_t)kT;
   L.take_at = L.head;
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
   if (t == 0) {
     L.head = 0, L.tail = 0, L.pushed = 0, L.sp_n = 0, L.gleft = 0, L.gpos = 0, L.ticket = -1;
     L.n1 = fs->n1;
-    L.n0 = fs->nchunks0;
+    L.n0 = (uint32_t)((L.n1 + kFlowChunk0 - 1) / kFlowChunk0);
   }
   uint64_t tokens = 0;
   int64_t walked = 0;  // thread 0
@@ -322,9 +329,15 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
       walked += n;
       L.pushed = 0;
       L.sp_n = 0;
+      // share what is beyond `keep`; while other workgroups are idle, what is
+      // beyond one round (the idle count is read only with such a backlog)
       const uint32_t occ = L.tail - L.head;
-      if (occ > (uint32_t)keep) {
-        const uint32_t sn = occ - (uint32_t)keep < (uint32_t)kT ? occ - (uint32_t)keep : (uint32_t)kT;
+      uint32_t kp = (uint32_t)keep;
+      if (occ > (uint32_t)kT && kp > (uint32_t)kT &&
+          __hip_atomic_load(&fs->idle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        kp = (uint32_t)kT;
+      if (occ > kp) {
+        const uint32_t sn = occ - kp < (uint32_t)kT ? occ - kp : (uint32_t)kT;
         const uint32_t base = atomicAdd(&fs->space, sn);
         if ((uint64_t)base + sn <= fb.qcap) {
           L.sp_base = base;
@@ -383,8 +396,6 @@ hipError_t launch_flow_kernel(const DevGrammar& g, LoadCounters* lc, FlowState* 
 
 hipError_t launch_flow_walk(const DevGrammar& g, LoadCounters* lc, FlowState* fs, const FlowBufs& fb,
                             const LevelParams& lp, int device, hipStream_t s) {
-  const hipError_t e = launch_fill_u64(fb.desc, fb.ndesc, 0, s);
-  if (e != hipSuccess) return e;
   if (lp.flow_group == 512) return launch_flow_kernel<512>(g, lc, fs, fb, lp.flow_keep * 512 / 1024, device, s);
   return launch_flow_kernel<1024>(g, lc, fs, fb, lp.flow_keep, device, s);
 }

@@ -46,10 +46,11 @@ __global__ __launch_bounds__(256) void k_zero_count(const uint64_t* pw, int64_t 
 __global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t R, const uint32_t* off,
                                                     int32_t* out, uint64_t* qw, FlowState* fs, const int64_t* n1p) {
   if (fs && blockIdx.x == 0 && threadIdx.x == 0) {
-    // the dataflow walk's queue starts with level 1 in chunks of kFlowChunk0
+    // the dataflow walk's queue starts with level 1 in rule-id order (low ids,
+    // the rules Sequitur made first, tend to head the deepest subtrees, so
+    // they start first)
     const int64_t n1 = *n1p;
     fs->n1 = n1;
-    fs->nchunks0 = (uint32_t)((n1 + kFlowChunk0 - 1) / kFlowChunk0);
     fs->live = n1;
     fs->space = (uint32_t)n1;
     fs->ticket = 0;

@@ -75,17 +75,15 @@ hipError_t launch_check_rules(const int64_t* rule_off, int64_t R, int64_t S, int
   return hipGetLastError();
 }
 
-// The same checks in one launch, with the zero fills of the load's
-// histograms and the dataflow walk's counters (one launch instead of six
-// keeps the GPU from waiting for the host at the start of a load): rule
-// offsets and the tile table (k_check_rules, k_root_tiles), file spans
-// (k_check_files), and zeros over wc_off, rc_off and `zero`. lc must be
-// zero before the launch.
+// The same checks in one launch, with the zero fills the dataflow load
+// needs (one launch instead of eight keeps the GPU from waiting for the
+// host at the start of a load): rule offsets and the tile table
+// (k_check_rules, k_root_tiles), file spans (k_check_files), and zeros over
+// the word counts of `z` (the offset histograms, the packed words, the
+// walk's counters and chunk descriptors). lc must be zero before the launch.
 __global__ __launch_bounds__(256) void k_load_prologue(const int64_t* rule_off, int64_t R, int64_t S,
                                                        const int64_t* file_off, int64_t F, int32_t* tile_rule,
-                                                       int64_t ntiles, LoadCounters* lc, uint32_t* wc_off,
-                                                       int64_t n_wc, uint32_t* rc_off, int64_t n_rc, uint32_t* zero,
-                                                       int64_t n_zero) {
+                                                       int64_t ntiles, LoadCounters* lc, ZeroRanges z) {
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   uint32_t bad = 0;
@@ -112,19 +110,18 @@ __global__ __launch_bounds__(256) void k_load_prologue(const int64_t* rule_off, 
     const int64_t a = file_off[f], b = file_off[f + 1];
     if (a > b || (f == 0 && a != 0) || (f == F - 1 && b != root_end)) bad |= ST_BAD_FILES;
   }
-  for (int64_t i = tid; i < n_wc; i += nth) wc_off[i] = 0;
-  for (int64_t i = tid; i < n_rc; i += nth) rc_off[i] = 0;
-  for (int64_t i = tid; i < n_zero; i += nth) zero[i] = 0;
+  for (int r = 0; r < z.count; ++r)
+    for (int64_t i = tid; i < z.n[r]; i += nth) z.p[r][i] = 0;
   if (bad) atomicOr(&lc->status, bad);
 }
 
 hipError_t launch_load_prologue(const int64_t* rule_off, int64_t R, int64_t S, const int64_t* file_off, int64_t F,
-                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, uint32_t* wc_off, int64_t n_wc,
-                                uint32_t* rc_off, int64_t n_rc, uint32_t* zero, int64_t n_zero, hipStream_t s) {
+                                int32_t* tile_rule, int64_t ntiles, LoadCounters* lc, const ZeroRanges& z,
+                                hipStream_t s) {
   int64_t n = R > ntiles ? R : ntiles;
   if (F > n) n = F;
-  k_load_prologue<<<fill_blocks(n), 256, 0, s>>>(rule_off, R, S, file_off, F, tile_rule, ntiles, lc, wc_off, n_wc,
-                                                 rc_off, n_rc, zero, n_zero);
+  for (int r = 0; r < z.count; ++r) n = z.n[r] > n ? z.n[r] : n;
+  k_load_prologue<<<fill_blocks(n), 256, 0, s>>>(rule_off, R, S, file_off, F, tile_rule, ntiles, lc, z);
   return hipGetLastError();
 }
 
@@ -294,6 +291,7 @@ __global__ __launch_bounds__(kRcThreads) void k_ref_reduce(DevGrammar g, const u
   __shared__ uint32_t in_root[kRcBucket];
   __shared__ uint32_t in_rules[kRcBucket];
   __shared__ int first_bucket;
+  if (blockIdx.x == 0 && threadIdx.x == 0) g.w[0] = 1;  // the root's weight (never packed: no in-edges)
   const int64_t n = *total;
   const int64_t c_lo = (int64_t)blockIdx.x * kRcChunk;
   if (c_lo >= n) return;  // uniform for the block
@@ -341,10 +339,13 @@ __global__ __launch_bounds__(kRcThreads) void k_ref_reduce(DevGrammar g, const u
   }
 }
 
-hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s) {
+hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64_t* n, LoadCounters* lc, hipStream_t s,
+                             bool w_zeroed) {
   if (g.rc_nb == 0) return hipSuccess;  // counted with direct atomics by the scan
-  hipError_t e0 = launch_fill_u64(g.w, g.R, 0, s);
-  if (e0 != hipSuccess) return e0;
+  if (!w_zeroed) {
+    const hipError_t e0 = launch_fill_u64(g.w, g.R, 0, s);
+    if (e0 != hipSuccess) return e0;
+  }
   if (g.ntiles > 0) {
     const size_t shmem = sizeof(int32_t) * (kTileRuleSlots + g.rc_nb);
     k_ref_scatter<<<(unsigned)g.nblk, kScanThreads, shmem, s>>>(g, entries, lc);
@@ -354,9 +355,8 @@ hipError_t launch_in_degrees(const DevGrammar& g, uint16_t* entries, const int64
   // at most S entries; chunks past the actual count exit at once
   const int64_t chunks = (g.S + kRcChunk - 1) / kRcChunk;
   if (chunks > 0) {
-    k_ref_reduce<<<(unsigned)chunks, kRcThreads, 0, s>>>(g, entries, n, lc);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    k_ref_reduce<<<(unsigned)chunks, kRcThreads, 0, s>>>(g, entries, n, lc);  // also sets the root's weight
+    return hipGetLastError();
   }
   k_fill_u64<<<1, 64, 0, s>>>(g.w, 1, 1);  // the root's weight (never packed: the root has no in-edges)
   return hipGetLastError();
