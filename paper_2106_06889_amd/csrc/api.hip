@@ -415,8 +415,9 @@ bool run_degrees(Call& call, gt::DevGrammar& d, gt::LoadCounters* lc, uint32_t* 
       (!zeroed && n_rc_off &&
        !hip_ok(gt::launch_fill_i32(reinterpret_cast<int32_t*>(d.rc_off), n_rc_off, 0, s), "fill")) ||
       !hip_ok(gt::launch_scan_symbols(d, lc, s), "scan_symbols") ||
-      (n_wc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.wc_off, n_wc_off, &lc->wc_entries, sums, s), "scan offsets")) ||
-      (n_rc_off > 0 && !hip_ok(gt::launch_scan_offsets(d.rc_off, n_rc_off, &lc->rc_entries, sums, s), "scan offsets")) ||
+      !hip_ok(gt::launch_scan_offsets2(d.wc_off, n_wc_off, &lc->wc_entries, d.rc_off, n_rc_off, &lc->rc_entries, sums,
+                                       s),
+              "scan offsets") ||
       (atomic_degrees && !hip_ok(gt::launch_fill_u64(d.w, 1, 1, s), "fill")))
     return false;
   if (!atomic_degrees) {
@@ -513,7 +514,7 @@ int gtadoc_load_grammar(gtadoc_ctx ctx, const int64_t* rule_off, int64_t R, cons
   }
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
-  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
+  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan2_scratch_entries(n_wc_off, n_rc_off),
                                                     nbR + gt::scan_scratch_entries(nbR) + 2}));
   if (!tile_rule || !d.w || !d.level_rule || !d.level_off || !lc || !sums || (want_levels && !level_cnt) ||
       (!want_levels && (!flow.qw || !flow.desc || !fs)) || (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
@@ -665,7 +666,7 @@ int ensure_levels(gtadoc_grammar g, void* stream) {
   int32_t* level_cnt = call.scratch<int32_t>(R + 2);
   auto* lc = call.scratch<gt::LoadCounters>(1);
   const int64_t nbR = (R + 4095) / 4096;
-  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan_scratch_entries(n_wc_off), gt::scan_scratch_entries(n_rc_off),
+  uint32_t* sums = call.scratch<uint32_t>(std::max({gt::scan2_scratch_entries(n_wc_off, n_rc_off),
                                                     nbR + gt::scan_scratch_entries(nbR) + 2}));
   if (!d.w || !level_cnt || !lc || !sums || (d.wc_nb && !d.wc_off) || (d.rc_nb && !d.rc_off))
     return oom("level buffers", 16 * (uint64_t)R + 4 * (uint64_t)(n_wc_off + n_rc_off));

@@ -236,6 +236,11 @@ struct BatchDesc {
 };
 hipError_t launch_word_count_batch(const BatchDesc* d, int grid_scatter, int grid_reduce, int max_nb, hipStream_t s);
 hipError_t launch_scan_offsets(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s);
+// both arrays (either may be empty) in three launches; sums needs
+// scan2_scratch_entries(na, nb)
+hipError_t launch_scan_offsets2(uint32_t* a, int64_t na, int64_t* ta, uint32_t* b, int64_t nb, int64_t* tb,
+                                uint32_t* sums, hipStream_t s);
+int64_t scan2_scratch_entries(int64_t na, int64_t nb);
 int64_t scan_scratch_entries(int64_t n);
 struct SortScratch {
   uint64_t* key[2];

@@ -380,6 +380,113 @@ hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s) {
 hipError_t launch_scan_offsets(uint32_t* a, int64_t n, int64_t* total, uint32_t* sums, hipStream_t s) {
   return launch_scan_u32(a, n, total, sums, s);
 }
+
+// Both offset histograms of the load scanned in three launches instead of
+// six: chunk sums of a (blocks [0, ca)) and b (blocks [ca, ca + cb)), one
+// workgroup scanning each half of the sums from zero (totals to *ta, *tb),
+// then every chunk rewritten with its offset.
+struct Scan2 {
+  uint32_t* a;
+  int64_t na;
+  uint32_t* b;
+  int64_t nb;
+  int64_t ca, cb;  // chunks of kRadixTile elements
+};
+
+__device__ __forceinline__ void scan2_chunk(const Scan2& q, uint32_t*& arr, int64_t& n, int64_t& chunk) {
+  if ((int64_t)blockIdx.x < q.ca) arr = q.a, n = q.na, chunk = blockIdx.x;
+  else arr = q.b, n = q.nb, chunk = blockIdx.x - q.ca;
+}
+
+__global__ __launch_bounds__(256) void k_scan2_sums(Scan2 q, uint32_t* sums) {
+  uint32_t* arr;
+  int64_t n, chunk;
+  scan2_chunk(q, arr, n, chunk);
+  const int64_t i0 = chunk * kRadixTile + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) c += arr[i0 + k];
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  block_exclusive_scan_256(c, lds, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of a[0..n) in place by the whole (1024-thread) workgroup.
+__device__ __forceinline__ void block_scan_inplace(uint32_t* a, int64_t n, int64_t* total, uint64_t* wsum) {
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = threadIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  uint64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += a[i];
+  uint64_t x = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(x, o);
+    if (lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < (int)(threadIdx.x >> 6)) base += wsum[w];
+    tot += wsum[w];
+  }
+  uint64_t run = base + x - s;
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint32_t c = a[i];
+    a[i] = (uint32_t)run;
+    run += c;
+  }
+  if (threadIdx.x == 0 && total) *total = (int64_t)tot;
+  __syncthreads();  // wsum is reused
+}
+
+__global__ __launch_bounds__(1024) void k_scan2_mid(uint32_t* sums, int64_t ca, int64_t cb, int64_t* ta, int64_t* tb) {
+  __shared__ uint64_t wsum[16];
+  block_scan_inplace(sums, ca, ta, wsum);
+  block_scan_inplace(sums + ca, cb, tb, wsum);
+}
+
+__global__ __launch_bounds__(256) void k_scan2_apply(Scan2 q, const uint32_t* sums) {
+  uint32_t* arr;
+  int64_t n, chunk;
+  scan2_chunk(q, arr, n, chunk);
+  const int64_t i0 = chunk * kRadixTile + threadIdx.x * 16;
+  uint32_t v[16], c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = (i0 + k < n) ? arr[i0 + k] : 0u;
+    c += v[k];
+  }
+  __shared__ uint32_t lds[4];
+  uint32_t total;
+  uint32_t run = sums[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (i0 + k < n) {
+      arr[i0 + k] = run;
+      run += v[k];
+    }
+}
+
+hipError_t launch_scan_offsets2(uint32_t* a, int64_t na, int64_t* ta, uint32_t* b, int64_t nb, int64_t* tb,
+                                uint32_t* sums, hipStream_t s) {
+  Scan2 q{a, na, b, nb, (na + kRadixTile - 1) / kRadixTile, (nb + kRadixTile - 1) / kRadixTile};
+  if (q.ca + q.cb == 0) return hipSuccess;
+  k_scan2_sums<<<(unsigned)(q.ca + q.cb), 256, 0, s>>>(q, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan2_mid<<<1, 1024, 0, s>>>(sums, q.ca, q.cb, ta, tb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_scan2_apply<<<(unsigned)(q.ca + q.cb), 256, 0, s>>>(q, sums);
+  return hipGetLastError();
+}
+int64_t scan2_scratch_entries(int64_t na, int64_t nb) {
+  return (na + kRadixTile - 1) / kRadixTile + (nb + kRadixTile - 1) / kRadixTile + 1;
+}
 int64_t scan_scratch_entries(int64_t n) { return scan_sums_entries(n); }
 
 }  // namespace gt
