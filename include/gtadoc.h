@@ -293,6 +293,8 @@ int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void
                                           queue (0..7168; default 4096) */
 #define GTADOC_PARAM_FLOW_GROUP 11      /* load, dataflow walk: threads per workgroup, 512 (two per CU) or
                                           1024 (default) */
+#define GTADOC_PARAM_FLOW_CHUNK 12      /* load, dataflow walk: rules per chunk of level 1 in its queue
+                                          (1..65535; default 128) */
 
 /* Set / get a tunable. Errors: INVALID_ARG (unknown parameter or value). */
 int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value);

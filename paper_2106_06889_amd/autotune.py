@@ -37,7 +37,7 @@ NAMES = {gt.PARAM_BATCH_BLOCKS_PER_CU: "batch_blocks_per_cu", gt.PARAM_WC_CHUNK:
          gt.PARAM_LEVEL_WIDE: "level_wide", gt.PARAM_LEVEL_LONG_BODY: "level_long_body",
          gt.PARAM_LEVEL_MID_RULES: "level_mid_rules", gt.PARAM_LEVEL_MID_BLOCKS: "level_mid_blocks",
          gt.PARAM_LEVEL_TAIL_RULES: "level_tail_rules", gt.PARAM_FLOW_KEEP: "flow_keep",
-         gt.PARAM_FLOW_GROUP: "flow_group"}
+         gt.PARAM_FLOW_GROUP: "flow_group", gt.PARAM_FLOW_CHUNK: "flow_chunk"}
 
 # the load (level walk) and the single-grammar word count, in search order
 LOAD_CANDIDATES = {
@@ -52,11 +52,12 @@ LOAD_DEFAULTS = {gt.PARAM_LEVEL_WIDE: 262144, gt.PARAM_LEVEL_MID_RULES: 49152, g
                  gt.PARAM_LEVEL_TAIL_RULES: 1024, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 32768}
 # the load by the dataflow walk (no levels) and the word count
 FLOW_CANDIDATES = {
-    gt.PARAM_FLOW_GROUP: [512, 1024],
+    gt.PARAM_FLOW_CHUNK: [64, 128, 256, 512],
     gt.PARAM_FLOW_KEEP: [1024, 2048, 4096, 7168],
     gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
 }
-FLOW_DEFAULTS = {gt.PARAM_FLOW_GROUP: 1024, gt.PARAM_FLOW_KEEP: 4096, gt.PARAM_WC_CHUNK: 32768}
+FLOW_DEFAULTS = {gt.PARAM_FLOW_CHUNK: 128, gt.PARAM_FLOW_GROUP: 1024, gt.PARAM_FLOW_KEEP: 4096,
+                 gt.PARAM_WC_CHUNK: 32768}
 
 
 def arch() -> str:

@@ -1470,6 +1470,10 @@ int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
       if (value < 0 || value > 7168) return fail(GTADOC_ERR_INVALID_ARG, "ring threshold out of range (0..7168)");
       ctx->level.flow_keep = (int32_t)value;
       return GTADOC_OK;
+    case GTADOC_PARAM_FLOW_CHUNK:
+      if (value < 1 || value > 65535) return fail(GTADOC_ERR_INVALID_ARG, "level-1 chunk out of range (1..65535)");
+      ctx->level.flow_chunk = (int32_t)value;
+      return GTADOC_OK;
     case GTADOC_PARAM_FLOW_GROUP:
       if (value != 512 && value != 1024) return fail(GTADOC_ERR_INVALID_ARG, "dataflow workgroup size must be 512 or 1024");
       ctx->level.flow_group = (int32_t)value;
@@ -1495,6 +1499,7 @@ int gtadoc_ctx_get_param(gtadoc_ctx ctx, int param, int64_t* value) {
     case GTADOC_PARAM_LEVEL_TAIL_RULES: *value = ctx->level.tail_rules; break;
     case GTADOC_PARAM_FLOW_KEEP: *value = ctx->level.flow_keep; break;
     case GTADOC_PARAM_FLOW_GROUP: *value = ctx->level.flow_group; break;
+    case GTADOC_PARAM_FLOW_CHUNK: *value = ctx->level.flow_chunk; break;
     default: return fail(GTADOC_ERR_INVALID_ARG, "unknown parameter %d", param);
   }
   return GTADOC_OK;

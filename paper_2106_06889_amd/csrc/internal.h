@@ -174,7 +174,8 @@ hipError_t prepare_level_walk(const DevGrammar& g, LoadCounters* lc, uint32_t* s
 //              workgroup's ring at the end of a round and shares the rest
 //              (per 1024 threads);
 //  flow_group  threads per workgroup of the dataflow walk (512: two
-//              workgroups per CU, or 1024).
+//              workgroups per CU, or 1024);
+//  flow_chunk  rules per level-1 chunk of the dataflow walk's queue.
 struct LevelParams {
   int32_t long_body = 32;
   int32_t mid_rules = 48 * 1024;
@@ -182,6 +183,7 @@ struct LevelParams {
   int32_t tail_rules = 1024;
   int32_t flow_keep = 4096;
   int32_t flow_group = 1024;
+  int32_t flow_chunk = 128;
 };
 hipError_t launch_level_walk(const DevGrammar& g, int32_t* level_cnt, LoadCounters* lc, uint32_t* scratch,
                              const WideBufs& wide, const LevelParams& params, int device, hipStream_t s);
@@ -199,7 +201,6 @@ struct FlowState {
   uint32_t nspill;    // chunks published beyond level 1
   uint32_t idle;      // workgroups waiting for work
 };
-constexpr int kFlowChunk0 = 1024;  // rules per level-1 chunk of the dataflow walk's queue
 struct FlowBufs {
   int32_t* qc;     // [qcap] rules (level_rule)
   uint64_t* qw;    // [qcap] their final weights

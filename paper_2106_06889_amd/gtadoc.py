@@ -82,7 +82,7 @@ EXPORTS = {
 }
 PARAM_WC_CHUNK, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAPH, PARAM_TIMING, PARAM_LEVEL_WIDE = 1, 2, 3, 4, 5
 PARAM_LEVEL_LONG_BODY, PARAM_LEVEL_MID_RULES, PARAM_LEVEL_MID_BLOCKS, PARAM_LEVEL_TAIL_RULES = 6, 7, 8, 9
-PARAM_FLOW_KEEP, PARAM_FLOW_GROUP = 10, 11
+PARAM_FLOW_KEEP, PARAM_FLOW_GROUP, PARAM_FLOW_CHUNK = 10, 11, 12
 PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6,
           "decompress": 7, "tv_topdown": 8}
 TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN = 0, 1, 2

@@ -202,21 +202,23 @@ def test_vocabulary_beyond_bucket_table(ctx):
     check_wc_sort(ctx, g, expect_tokens=3000)
 
 
-@pytest.mark.parametrize("keep,group", [(0, 1024), (64, 512), (4096, 1024), (7168, 512), (1024, 512)])
-def test_dataflow_walk_shapes(ctx, keep, group):
+@pytest.mark.parametrize("keep,group,chunk", [(0, 1024, 128), (64, 512, 1), (4096, 1024, 7), (7168, 512, 4096),
+                                              (1024, 512, 65535), (1024, 1024, 128)])
+def test_dataflow_walk_shapes(ctx, keep, group, chunk):
     """The dataflow walk with rings that share everything beyond 0 or 64
     rules (many published chunks) or keep up to 7168, in workgroups of 512
-    or 1024 threads: the same counts as the oracle on recipe-scaled corpora
-    and random ones."""
+    or 1024 threads, with level-1 chunks of 1 to 65535 rules: the same counts
+    as the oracle on recipe-scaled corpora and random ones."""
     import paper_2106_06889_amd as gt
     cases = [synth.workload("wc-100m", scale=0.02), synth.workload("seq-20m", scale=0.02),
              synth.workload("tv-4000files", scale=0.005)]
     for seed in (6, 7):
         c = synth.random_corpus(seed, 2, 5000, [40, 900][seed % 2])
         cases.append((c, synth.compress(c.tokens, c.file_off, c.vocab)))
-    old = ctx.get_param(gt.PARAM_FLOW_KEEP), ctx.get_param(gt.PARAM_FLOW_GROUP)
+    old = ctx.get_param(gt.PARAM_FLOW_KEEP), ctx.get_param(gt.PARAM_FLOW_GROUP), ctx.get_param(gt.PARAM_FLOW_CHUNK)
     ctx.set_param(gt.PARAM_FLOW_KEEP, keep)
     ctx.set_param(gt.PARAM_FLOW_GROUP, group)
+    ctx.set_param(gt.PARAM_FLOW_CHUNK, chunk)
     try:
         for c, g in cases:
             G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab)
@@ -228,6 +230,7 @@ def test_dataflow_walk_shapes(ctx, keep, group):
     finally:
         ctx.set_param(gt.PARAM_FLOW_KEEP, old[0])
         ctx.set_param(gt.PARAM_FLOW_GROUP, old[1])
+        ctx.set_param(gt.PARAM_FLOW_CHUNK, old[2])
 
 
 def test_dataflow_ring_overflow(ctx):
