@@ -854,25 +854,16 @@ int gtadoc_sort(gtadoc_grammar g, const uint64_t* word_counts, uint32_t* ids, ui
 
 namespace {
 
-// Byte mask of the packed n-gram keys: word ids < V occupy bitlen(V-1) bits
-// at bit 0 and 32 (n = 2) or at bits 0, 21 and 42 (n = 3).
-uint64_t gram_byte_mask(int n, int32_t V) {
+// The bits of the packed n-gram keys that word ids < V can occupy:
+// bitlen(V-1) bits at bits 0 and 32 (n = 2), 0, 21 and 42 (n = 3), or 0, 16,
+// 32 and 48 (n = 4); all other bits are zero.
+gt::KeyBits gram_key_bits(int n, int32_t V) {
   const int b = std::max(1, bitlen((uint64_t)(V - 1)));
-  uint64_t mask = 0;
-  auto cover = [&](int lo, int hi) {
-    for (int x = lo / 8; x * 8 < hi && x < 8; ++x) mask |= 1ull << x;
-  };
-  if (n == 2) {
-    cover(0, b);
-    cover(32, 32 + b);
-  } else if (n == 4) {
-    for (int x = 0; x < 4; ++x) cover(16 * x, 16 * x + b);
-  } else {
-    cover(0, b);
-    cover(21, 21 + b);
-    cover(42, 42 + b);
-  }
-  return mask;
+  gt::KeyBits kb{};
+  const int step = n == 2 ? 32 : (n == 3 ? 21 : 16);
+  kb.nseg = n;
+  for (int x = 0; x < n; ++x) kb.lo[x] = step * x, kb.len[x] = b;
+  return kb;
 }
 
 gtadoc_result new_result(gtadoc_ctx ctx) {
@@ -1297,7 +1288,7 @@ int sequence_count_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* out) 
   auto* v0 = call.scratch<uint64_t>(U);
   auto* k1 = call.scratch<uint64_t>(U);
   auto* v1 = call.scratch<uint64_t>(U);
-  auto* hist = call.scratch<uint32_t>(gt::sort_scratch_hist_entries(U));
+  auto* hist = call.scratch<uint32_t>(gt::key_sort_hist_entries(U));
   if (!okey || !oval || !k0 || !v0 || !k1 || !v1 || !hist) {
     release_all(g->ctx, res->blocks);
     delete res;
@@ -1306,7 +1297,7 @@ int sequence_count_run(gtadoc_grammar g, int n, Call& call, gtadoc_result* out) 
   if (U > 0) {
     hipError_t e = gt::launch_occ_write(table, (int64_t)cap, cnt, k0, v0, s);
     if (e == hipSuccess)
-      e = gt::launch_sort_keys_u64(k0, v0, k1, v1, flags, U, gram_byte_mask(n, d.V), hist, okey, oval, s);
+      e = gt::launch_sort_key_bits(k0, v0, k1, v1, U, gram_key_bits(n, d.V), hist, okey, oval, s);
     if (e != hipSuccess) {
       (void)hipStreamSynchronize(s);
       release_all(g->ctx, res->blocks);

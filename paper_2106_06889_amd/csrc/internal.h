@@ -192,14 +192,17 @@ hipError_t launch_unpack_weights(const DevGrammar& g, hipStream_t s);
 
 // Dataflow walk (weights without levels): the global queue of ready rules
 // (level 1 first, with their weights) and the descriptors of the chunks
-// published into it; counters in FlowState.
+// published into it; counters in FlowState. Waiting workgroups poll `live`
+// and working ones take tickets and queue space, so the groups of counters
+// sit on separate 256-byte lines: atomics on one line are served one after
+// the other, and polls would otherwise queue the working side's atomics.
 struct FlowState {
-  int64_t live;       // rules queued anywhere or being walked
-  int64_t n1;         // rules of level 1
-  uint32_t space;     // queue entries reserved (level 1 first)
-  uint32_t ticket;    // next chunk ticket
-  uint32_t nspill;    // chunks published beyond level 1
-  uint32_t idle;      // workgroups waiting for work
+  alignas(256) int64_t live;  // rules queued anywhere or being walked
+  alignas(256) uint32_t ticket;  // next chunk ticket
+  uint32_t space;              // queue entries reserved (level 1 first)
+  uint32_t nspill;             // chunks published beyond level 1
+  alignas(256) uint32_t idle;  // workgroups waiting for work
+  alignas(256) int64_t n1;     // rules of level 1
 };
 struct FlowBufs {
   int32_t* qc;     // [qcap] rules (level_rule)
@@ -250,6 +253,19 @@ struct SortScratch {
 };
 int64_t sort_scratch_hist_entries(int64_t n);
 int64_t word_sort_hist_entries(int64_t V);
+// The bits of a 64-bit key that can differ between keys: nseg (1..4) ranges
+// [lo[i], lo[i] + len[i]), ascending and disjoint; every other bit is the
+// same in all keys.
+struct KeyBits {
+  int nseg;
+  int lo[4], len[4];
+};
+int64_t key_sort_hist_entries(int64_t n);
+// Stable ascending LSD sort of n < 2^32 (key, value) pairs on the bits kb
+// names: input (k0, v0), scratch (k1, v1), result in (kout, vout), which may
+// not alias the input or the scratch; hist holds key_sort_hist_entries(n).
+hipError_t launch_sort_key_bits(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, int64_t n,
+                                const KeyBits& kb, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s);
 
 // term vector / inverted index
 struct TvFiles {
@@ -338,8 +354,6 @@ hipError_t launch_occ_count(const uint64_t* table, int64_t cap, uint32_t* cnt, i
                             hipStream_t s);
 hipError_t launch_occ_write(const uint64_t* table, int64_t cap, const uint32_t* off, uint64_t* okey, uint64_t* oval,
                             hipStream_t s);
-hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
-                                uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s);
 hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bits, SortScratch& sc, uint32_t* ids_out,
                                 uint64_t* cnt_out, int64_t* num_out, hipStream_t s);
 

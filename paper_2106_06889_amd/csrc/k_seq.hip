@@ -36,16 +36,12 @@ constexpr uint64_t kEmptyKey = ~0ull;  // never a valid packed n-gram
 // head[4r ..] = first min(len, kHT) words of exp(r), tail[4r ..] = last
 // min(len, kHT) words in text order (unused entries -1; rows padded to 16
 // bytes so a row is one vector load); len[r] = words in exp(r). kHT = 3
-// serves every n <= 4. Rules of one level; their children (deeper levels)
-// are done.
+// serves every n <= 4. The rule's children (deeper levels) are done.
 constexpr int kHT = 3;
 constexpr int kHTRow = 4;
 
-__global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
-                                 int32_t* tail) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t r = rules[i];
+__device__ __forceinline__ void headtail_rule(const DevGrammar& g, int32_t r, uint64_t* len, int32_t* head,
+                                              int32_t* tail) {
   const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
   uint64_t L = 0;
   int32_t h[kHT] = {-1, -1, -1};
@@ -87,14 +83,50 @@ __global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, 
   *reinterpret_cast<v4i32*>(tail + kHTRow * (int64_t)r) = tv;
 }
 
+// One level, a thread per rule.
+__global__ void k_headtail_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
+                                 int32_t* tail) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) headtail_rule(g, rules[i], len, head, tail);
+}
+
+// A run of narrow levels, deepest (d_hi) first, in one workgroup: a
+// workgroup barrier between levels instead of a launch per level (deep
+// grammars end in long chains of levels of a few rules each).
+constexpr int kHeadtailNarrowThreads = 1024;
+__global__ __launch_bounds__(kHeadtailNarrowThreads) void k_headtail_narrow(DevGrammar g, int32_t d_lo, int32_t d_hi,
+                                                                            uint64_t* len, int32_t* head,
+                                                                            int32_t* tail) {
+  for (int32_t d = d_hi; d >= d_lo; --d) {
+    const int32_t lo = g.level_off[d], hi = g.level_off[d + 1];
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kHeadtailNarrowThreads)
+      headtail_rule(g, g.level_rule[i], len, head, tail);
+    __syncthreads();  // the next level reads what this one wrote
+  }
+}
+
 hipError_t launch_headtail(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
                            int32_t* head, int32_t* tail, hipStream_t s) {
-  for (int32_t d = depth; d >= 1; --d) {
+  for (int32_t d = depth; d >= 1;) {
     const int32_t lo = level_off_host[d], hi = level_off_host[d + 1];
-    if (hi <= lo) continue;
-    k_headtail_level<<<(unsigned)((hi - lo + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, hi - lo, len, head, tail);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (hi - lo <= kHeadtailNarrowThreads) {
+      int32_t d_lo = d;  // the run of narrow levels from d upwards
+      while (d_lo > 1 && level_off_host[d_lo] - level_off_host[d_lo - 1] <= kHeadtailNarrowThreads) --d_lo;
+      if (d_lo < d) {
+        k_headtail_narrow<<<1, kHeadtailNarrowThreads, 0, s>>>(g, d_lo, d, len, head, tail);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        d = d_lo - 1;
+        continue;
+      }
+    }
+    if (hi > lo) {
+      k_headtail_level<<<(unsigned)((hi - lo + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, hi - lo, len, head,
+                                                                         tail);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    --d;
   }
   return hipSuccess;
 }
@@ -300,7 +332,6 @@ hipError_t launch_seq_windows(const DevGrammar& g, int n, const uint64_t* len, c
   return hipGetLastError();
 }
 
-// Compaction of the occupied slots (slot order), then the caller sorts.
 // Compaction of the occupied slots (any order: a radix sort follows). Slot
 // i0 + k * 256 + thread for k < 16: the lanes of a wave read consecutive
 // slots, one line per 8 lanes.
@@ -318,26 +349,41 @@ __global__ __launch_bounds__(256) void k_occ_count(const uint64_t* table, int64_
   if (threadIdx.x == 0) cnt[blockIdx.x] = total;
 }
 
+// The block's output is ordered by (step k, wave, lane), so the occupied
+// lanes of one wave step write consecutive positions.
+typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_occ_write(const uint64_t* table, int64_t cap, const uint32_t* off,
                                                    uint64_t* okey, uint64_t* oval) {
   const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
-  uint64_t kv[16];
-  uint32_t c = 0;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  __shared__ uint32_t start[16][4];  // per (step, wave): count, then first output position
+  v2u64 kv[16];
+  uint64_t occ[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int64_t i = i0 + k * 256;
-    kv[k] = i < cap ? __builtin_nontemporal_load(table + 2 * i) : kEmptyKey;
-    c += kv[k] != kEmptyKey;
+    kv[k] = i < cap ? __builtin_nontemporal_load(reinterpret_cast<const v2u64*>(table) + i) : v2u64{kEmptyKey, 0};
+    occ[k] = __ballot(kv[k].x != kEmptyKey);
+    if (lane == 0) start[k][wave] = (uint32_t)__popcll(occ[k]);
   }
-  __shared__ uint32_t lds[4];
-  uint32_t total;
-  uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+  __syncthreads();
+  if (wave == 0) {  // exclusive scan of the 64 counts in (k, wave) order
+    const uint32_t v = start[lane >> 2][lane & 3];
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    start[lane >> 2][lane & 3] = off[blockIdx.x] + x - v;
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (kv[k] != kEmptyKey) {
-      okey[pos] = kv[k];
-      oval[pos] = table[2 * (i0 + k * 256) + 1];
-      ++pos;
+    if (kv[k].x != kEmptyKey) {
+      const uint32_t pos = start[k][wave] + (uint32_t)__popcll(occ[k] & lanes_below());
+      okey[pos] = kv[k].x;
+      oval[pos] = kv[k].y;
     }
 }
 
@@ -357,9 +403,5 @@ hipError_t launch_occ_write(const uint64_t* table, int64_t cap, const uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_sort_keys_u64(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, const int64_t* num, int64_t cap,
-                                uint64_t byte_mask, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s) {
-  return radix_sort_pairs_bytes<uint64_t>(k0, v0, k1, v1, num, cap, byte_mask, false, hist, kout, vout, s);
-}
 
 }  // namespace gt

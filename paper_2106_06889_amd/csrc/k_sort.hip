@@ -15,6 +15,12 @@
 // consecutive keys, ranks equal digits by ballots over the digit bits and
 // keeps running counts per digit in LDS, and waves are ordered by a prefix
 // over their counts.
+//
+// The same passes sort the packed n-gram keys of the sequence count
+// ascending (launch_sort_key_bits): their digits are taken from the bits
+// that word ids can occupy only (36 bits for bigrams over a 2*10^5-word
+// vocabulary, 4 passes instead of one per occupied byte), with the counts as
+// 64-bit values.
 #include "device.h"
 #include "radix.h"
 
@@ -28,10 +34,30 @@ constexpr int kWsMaxBits = 9;
 constexpr int kWsMaxDigits = 1 << kWsMaxBits;
 constexpr int kWsColThreads = 256;
 
-// Digit of a count for a descending sort over the low `bits` bits.
-__device__ __forceinline__ uint32_t ws_digit(uint64_t count, int shift, int dbits) {
-  return (uint32_t)((~count >> shift) & ((1u << dbits) - 1u));
-}
+// Digit of a count for a descending sort: dbits bits of ~count at shift.
+struct CountDigit {
+  int shift, dbits;
+  __device__ __forceinline__ uint32_t operator()(uint64_t count) const {
+    return (uint32_t)((~count >> shift) & ((1u << dbits) - 1u));
+  }
+};
+
+// Digit of a key for an ascending sort over chosen bits: up to four bit
+// ranges of the key, [s[i], s[i] + l[i]), joined low to high.
+struct BitsDigit {
+  int dbits;
+  uint8_t s[4], l[4];
+  __device__ __forceinline__ uint32_t operator()(uint64_t k) const {
+    uint32_t d = 0;
+    int at = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (l[i]) d |= (uint32_t)((k >> s[i]) & ((1ull << l[i]) - 1u)) << at;
+      at += l[i];
+    }
+    return d;
+  }
+};
 
 // Lanes of the wave whose digit equals this lane's (among `valid` lanes).
 __device__ __forceinline__ uint64_t ws_peers(bool valid, uint32_t d, int dbits) {
@@ -46,11 +72,12 @@ __device__ __forceinline__ uint64_t ws_peers(bool valid, uint32_t d, int dbits) 
 
 // Digit histogram of every tile: hist[d * nb + tile]. The first pass reads
 // the counts and also writes the tile's number of zero counts.
-template <bool kFirst>
-__global__ __launch_bounds__(kWsThreads) void k_ws_hist(const uint64_t* keys, int64_t V, int shift, int dbits,
-                                                        uint32_t* hist, int nb, uint32_t* zeros) {
+template <bool kFirst, class Dig>
+__global__ __launch_bounds__(kWsThreads) void k_ws_hist(const uint64_t* keys, int64_t V, Dig dig, uint32_t* hist,
+                                                        int nb, uint32_t* zeros) {
   __shared__ uint32_t h[kWsMaxDigits];
   __shared__ uint32_t zs[kWsWaves];
+  const int dbits = dig.dbits;
   const int nd = 1 << dbits;
   for (int d = threadIdx.x; d < nd; d += kWsThreads) h[d] = 0;
   __syncthreads();
@@ -63,7 +90,7 @@ __global__ __launch_bounds__(kWsThreads) void k_ws_hist(const uint64_t* keys, in
     const bool valid = idx < V;
     const uint64_t k = valid ? keys[idx] : 0;
     if (kFirst) z += valid && k == 0;
-    const uint32_t d = ws_digit(k, shift, dbits);
+    const uint32_t d = dig(k);
     const uint64_t peers = ws_peers(valid, d, dbits);
     // one LDS add per distinct digit of the step (Zipf-hot digits would
     // otherwise serialize on one address)
@@ -108,16 +135,17 @@ __global__ __launch_bounds__(kWsColThreads) void k_ws_colscan(uint32_t* hist, in
   }
 }
 
-// Stable scatter of one pass. The first pass takes the counts as keys and
-// the positions as values.
-template <bool kFirst>
-__global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                           uint32_t* vout, int64_t V, int shift, int dbits,
-                                                           const uint32_t* hist, const uint32_t* tot, int nb) {
+// Stable scatter of one pass. The first pass of the count sort takes the
+// counts as keys and the positions as values.
+template <bool kFirst, class Dig, typename VT>
+__global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, const VT* vin, uint64_t* kout,
+                                                           VT* vout, int64_t V, Dig dig, const uint32_t* hist,
+                                                           const uint32_t* tot, int nb) {
   __shared__ uint32_t wcnt[kWsWaves][kWsMaxDigits];
   __shared__ uint32_t base[kWsWaves][kWsMaxDigits];
   __shared__ uint32_t dstart[kWsMaxDigits];
   __shared__ uint32_t part[kWsWaves];
+  const int dbits = dig.dbits;
   const int nd = 1 << dbits;
   const int wave = threadIdx.x >> 6, lane = lane_id();
   // digit starts: exclusive scan of the digit totals (nd <= 512 <= threads)
@@ -138,13 +166,14 @@ __global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, 
   }
   const int64_t t0 = (int64_t)blockIdx.x * kWsTile + (int64_t)wave * (kWsPer * 64);
   uint64_t key[kWsPer];
-  uint32_t val[kWsPer], rank[kWsPer], dig[kWsPer];
+  VT val[kWsPer];
+  uint32_t rank[kWsPer], dgt[kWsPer];
 #pragma unroll
   for (int j = 0; j < kWsPer; ++j) {
     const int64_t idx = t0 + j * 64 + lane;
     const bool valid = idx < V;
     const uint64_t k = valid ? kin[idx] : 0;
-    const uint32_t d = ws_digit(k, shift, dbits);
+    const uint32_t d = dig(k);
     const uint64_t peers = ws_peers(valid, d, dbits);
     const uint32_t before = wcnt[wave][d];
     const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
@@ -152,9 +181,9 @@ __global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, 
     if (valid && r == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
     key[j] = k;
-    val[j] = valid ? (kFirst ? (uint32_t)idx : vin[idx]) : 0u;
+    val[j] = valid ? (kFirst ? (VT)idx : vin[idx]) : VT(0);
     rank[j] = valid ? before + r : 0xffffffffu;
-    dig[j] = d;
+    dgt[j] = d;
   }
   __syncthreads();
   for (int d = threadIdx.x; d < nd; d += kWsThreads) {
@@ -168,7 +197,7 @@ __global__ __launch_bounds__(kWsThreads) void k_ws_scatter(const uint64_t* kin, 
 #pragma unroll
   for (int j = 0; j < kWsPer; ++j) {
     if (rank[j] == 0xffffffffu) continue;
-    const uint32_t pos = base[wave][dig[j]] + rank[j];
+    const uint32_t pos = base[wave][dgt[j]] + rank[j];
     kout[pos] = key[j];
     vout[pos] = val[j];
   }
@@ -198,15 +227,63 @@ hipError_t launch_sort_by_count(const uint64_t* counts, int32_t V, int key_bits,
     const bool last = p == npass - 1;
     uint64_t* kdst = last ? cnt_out : sc.key[p & 1];
     uint32_t* vdst = last ? ids_out : sc.val[p & 1];
-    if (p == 0) k_ws_hist<true><<<nb, kWsThreads, 0, s>>>(kin, V, shift, dbits, hist, nb, zeros);
-    else k_ws_hist<false><<<nb, kWsThreads, 0, s>>>(kin, V, shift, dbits, hist, nb, nullptr);
+    const CountDigit dig{shift, dbits};
+    if (p == 0) k_ws_hist<true><<<nb, kWsThreads, 0, s>>>(kin, V, dig, hist, nb, zeros);
+    else k_ws_hist<false><<<nb, kWsThreads, 0, s>>>(kin, V, dig, hist, nb, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_ws_colscan<<<1 << dbits, kWsColThreads, 0, s>>>(hist, nb, tot, p == 0 ? zeros : nullptr, V, num_out);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (p == 0) k_ws_scatter<true><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, shift, dbits, hist, tot, nb);
-    else k_ws_scatter<false><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, shift, dbits, hist, tot, nb);
+    if (p == 0) k_ws_scatter<true><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, dig, hist, tot, nb);
+    else k_ws_scatter<false><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, V, dig, hist, tot, nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    kin = kdst;
+    vin = vdst;
+  }
+  return hipSuccess;
+}
+
+int64_t key_sort_hist_entries(int64_t n) { return word_sort_hist_entries(n); }
+
+hipError_t launch_sort_key_bits(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1, int64_t n,
+                                const KeyBits& kb, uint32_t* hist, uint64_t* kout, uint64_t* vout, hipStream_t s) {
+  const int nb = (int)((n + kWsTile - 1) / kWsTile);
+  if (nb == 0) return hipSuccess;
+  int total = 0;
+  for (int i = 0; i < kb.nseg; ++i) total += kb.len[i];
+  if (kb.nseg < 1 || kb.nseg > 4 || total < 1 || total > 64 || n >= (1ll << 32)) return hipErrorInvalidValue;
+  const int npass = (total + kWsMaxBits - 1) / kWsMaxBits;
+  const int dbits = (total + npass - 1) / npass;
+  uint32_t* tot = hist + (int64_t)kWsMaxDigits * nb + nb;
+  const uint64_t* kin = k0;
+  const uint64_t* vin = v0;
+  int seg = 0, used = 0;  // next significant bit: bit `used` of segment `seg`
+  for (int p = 0; p < npass; ++p) {
+    BitsDigit dig{};
+    int want = dbits, parts = 0;
+    while (want > 0 && seg < kb.nseg) {
+      const int take = kb.len[seg] - used < want ? kb.len[seg] - used : want;
+      if (parts == 4) return hipErrorInvalidValue;
+      dig.s[parts] = (uint8_t)(kb.lo[seg] + used);
+      dig.l[parts] = (uint8_t)take;
+      ++parts;
+      want -= take;
+      used += take;
+      if (used == kb.len[seg]) ++seg, used = 0;
+    }
+    dig.dbits = dbits - want;
+    const bool last = p == npass - 1;
+    uint64_t* kdst = last ? kout : ((p & 1) == 0 ? k1 : k0);
+    uint64_t* vdst = last ? vout : ((p & 1) == 0 ? v1 : v0);
+    k_ws_hist<false><<<nb, kWsThreads, 0, s>>>(kin, n, dig, hist, nb, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ws_colscan<<<1 << dig.dbits, kWsColThreads, 0, s>>>(hist, nb, tot, nullptr, n, nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_ws_scatter<false><<<nb, kWsThreads, 0, s>>>(kin, vin, kdst, vdst, n, dig, hist, tot, nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     kin = kdst;
