@@ -22,9 +22,11 @@
  *    pool, Section "Data Structures"). The library never calls hipMalloc for
  *    them.
  *  - A context is driven by one host thread at a time. Calls on different
- *    streams are ordered by the context: a call waits for the work of the
- *    previous call on the same context (an event), so arena memory released
- *    by one call is never reused while another stream still reads it.
+ *    streams are ordered by the context: a call on another stream than the
+ *    previous call's records an event on that stream and waits for it, so
+ *    arena memory released by one call is never reused while another stream
+ *    still reads it (calls on one stream are ordered by the stream and
+ *    record no event). gtadoc_ctx_destroy waits for the whole device.
  *
  * Grammar encoding (CSR, identical for host and device inputs):
  *   rule_off int64[num_rules + 1]  body(r) = sym[rule_off[r] .. rule_off[r+1]);
@@ -280,7 +282,9 @@ int gtadoc_sequence_count_wide(gtadoc_grammar g, int n, gtadoc_result* out, void
 #define GTADOC_PARAM_BATCH_BLOCKS_PER_CU 2  /* batched word count: persistent scatter workgroups per CU */
 #define GTADOC_PARAM_BATCH_GRAPH 3       /* 1: replay a batch's launch sequence from a captured hipGraph */
 
-#define GTADOC_PARAM_TIMING 4          /* 1: record HIP events around the main kernels of every call */
+#define GTADOC_PARAM_TIMING 4          /* 1: record HIP events around the main kernels of every call;
+                                          other values: a mask, bit (p + 1) times phase p only (each
+                                          event pair leaves the GPU idle for a few microseconds) */
 #define GTADOC_PARAM_LEVEL_WIDE 5      /* load: levels of at least this many rules accumulate weights and
                                           in-edges by bucket instead of atomics (0: never; default 262144) */
 #define GTADOC_PARAM_LEVEL_LONG_BODY 6  /* load: rule bodies longer than this are walked by a whole

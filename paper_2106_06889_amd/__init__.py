@@ -7,4 +7,4 @@ from .gtadoc import (Batch, Context, PARAM_BATCH_BLOCKS_PER_CU, PARAM_BATCH_GRAP
                      QUERY_RANKED_INVERTED_INDEX, QUERY_SEQUENCE_COUNT, QUERY_TERM_VECTOR, QUERY_WORD_COUNT,
                      TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN, PARAM_LEVEL_LONG_BODY, PARAM_LEVEL_MID_BLOCKS,
                      PARAM_LEVEL_MID_RULES, PARAM_LEVEL_TAIL_RULES, PARAM_FLOW_KEEP, PARAM_FLOW_GROUP, PARAM_FLOW_CHUNK,
-                     LOAD_LEVELS)
+                     LOAD_LEVELS, timing_mask)

@@ -136,15 +136,15 @@ struct gtadoc_ctx_s {
   char* base = nullptr;
   Arena arena;
   int device = 0;
-  hipEvent_t done = nullptr;     // end of the most recent call's work
-  hipStream_t last = nullptr;    // stream of that call
-  bool has_done = false;
+  hipEvent_t done = nullptr;     // recorded on `last` when a call comes on another stream
+  hipStream_t last = nullptr;    // stream of the most recent call
+  bool has_done = false;         // there was such a call
   char* pinned = nullptr;        // small pinned host buffer for read-backs
   int64_t wc_chunk = 32 * 1024;  // word-count reduce chunk (tunable)
   int64_t batch_blocks_per_cu = 4;
   int64_t batch_graph = 0;
   int64_t param_epoch = 0;       // bumped on every parameter change (invalidates captured graphs)
-  int64_t timing = 0;            // record events around the main kernels of each call
+  int64_t timing = 0;            // phases timed: 1 all, else bit (p + 1) for phase p
   int64_t level_wide = 262144;   // level walk: bucketed mode from this many rules per level (0: never)
   gt::LevelParams level;         // level walk launch shape
   struct Timer {
@@ -211,7 +211,11 @@ namespace {
 
 // Orders a call after the previous call on the same context and owns the
 // call's scratch, which goes back to the arena when the call returns (later
-// calls are ordered after this one's work, so the reuse is safe).
+// calls are ordered after this one's work, so the reuse is safe). Calls on
+// one stream are ordered by the stream; a call on another stream records
+// an event on the previous call's stream when it begins and waits for it,
+// so no event is recorded between calls on one stream (each would leave
+// the GPU idle for a few microseconds).
 class Call {
  public:
   Call(gtadoc_ctx ctx, void* stream) : ctx_(ctx), s_(static_cast<hipStream_t>(stream)) {}
@@ -223,7 +227,10 @@ class Call {
   Call(gtadoc_ctx ctx, hipStream_t stream, std::vector<Block>* defer) : ctx_(ctx), s_(stream), defer_(defer) {}
   int begin() {
     if (hipSetDevice(ctx_->device) != hipSuccess) return fail(GTADOC_ERR_HIP, "hipSetDevice failed");
-    if (!defer_ && ctx_->has_done && ctx_->last != s_) HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
+    if (!defer_ && ctx_->has_done && ctx_->last != s_) {
+      HIP_TRY(hipEventRecord(ctx_->done, ctx_->last));
+      HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
+    }
     return GTADOC_OK;
   }
   ~Call() {
@@ -232,10 +239,8 @@ class Call {
       return;
     }
     for (const Block& b : scratch_) ctx_->arena.release(b);
-    if (hipEventRecord(ctx_->done, s_) == hipSuccess) {
-      ctx_->last = s_;
-      ctx_->has_done = true;
-    }
+    ctx_->last = s_;
+    ctx_->has_done = true;
   }
   // Scratch for this call only.
   template <typename T>
@@ -282,7 +287,7 @@ void fold_timer(gtadoc_ctx_s::Timer& t) {
 class PhaseScope {
  public:
   PhaseScope(gtadoc_ctx ctx, int phase, hipStream_t s) : ctx_(ctx), ph_(phase), s_(s) {
-    if (ctx_->timing) a_ = take();
+    if (ctx_->timing == 1 || ((ctx_->timing >> (ph_ + 1)) & 1)) a_ = take();
     if (a_ && hipEventRecord(a_, s_) != hipSuccess) give(a_), a_ = nullptr;
   }
   void end() {
@@ -370,7 +375,11 @@ int gtadoc_ctx_create(void* arena, uint64_t arena_bytes, gtadoc_ctx* out) {
 
 int gtadoc_ctx_destroy(gtadoc_ctx ctx) {
   if (!ctx) return fail(GTADOC_ERR_INVALID_ARG, "null context");
-  if (ctx->has_done) (void)hipEventSynchronize(ctx->done);
+  // the last call's stream may be gone by now: wait for the whole device
+  if (ctx->has_done) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+  }
   for (auto& t : ctx->timers) {
     fold_timer(t);
     for (hipEvent_t e : t.spare) (void)hipEventDestroy(e);
@@ -1435,7 +1444,8 @@ int gtadoc_ctx_set_param(gtadoc_ctx ctx, int param, int64_t value) {
       ctx->batch_graph = value ? 1 : 0;
       break;
     case GTADOC_PARAM_TIMING:
-      ctx->timing = value ? 1 : 0;
+      if (value < 0 || value >= (2ll << GTADOC_NUM_PHASES)) return fail(GTADOC_ERR_INVALID_ARG, "timing mask out of range");
+      ctx->timing = value;
       return GTADOC_OK;  // changes no launch sequence
     case GTADOC_PARAM_LEVEL_WIDE:
       if (value < 0) return fail(GTADOC_ERR_INVALID_ARG, "level width threshold out of range");

@@ -144,6 +144,9 @@ __device__ __forceinline__ void flow_push(FlowLds<kT>& L, FlowState* fs, const F
 // round, a ticket is taken; a level-1 chunk is there at once, a later one is
 // picked up once its descriptor is published. With neither ring entries nor
 // a range the workgroup waits for its chunk, or leaves when no work is left.
+// A long wait polls more slowly, and reads the live count only every 8th
+// time: polls of a counter queue with the atomics on its line, and at the
+// end of the walk most workgroups wait while a few walk the deepest rules.
 template <int kT>
 __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const FlowBufs& fb, uint32_t* status) {
   const uint32_t n0 = L.n0;
@@ -175,7 +178,8 @@ __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const
       atomicAdd(&fs->idle, 1u);
     }
     // zero only once every rule has been walked: the chunk will never come
-    if (__hip_atomic_load(&fs->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if ((it < 16 || (it & 7) == 0) &&
+        __hip_atomic_load(&fs->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       L.n = -1;
       return;
     }
@@ -184,7 +188,8 @@ __device__ __forceinline__ void flow_decide(FlowLds<kT>& L, FlowState* fs, const
       L.n = -1;
       return;
     }
-    __builtin_amdgcn_s_sleep(2);
+    if (it < 16) __builtin_amdgcn_s_sleep(2);
+    else __builtin_amdgcn_s_sleep(16);
   }
   if (idle) atomicSub(&fs->idle, 1u);
   const uint32_t occ = L.tail - L.head;

@@ -28,11 +28,8 @@ constexpr int kWHT = 7;       // head/tail words kept per rule (n - 1 <= 7)
 constexpr int kWRow = 8;      // row stride (32 bytes)
 constexpr uint64_t kWEmpty = ~0ull;
 
-__global__ void k_headtail_wide_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
-                                      int32_t* tail) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t r = rules[i];
+__device__ __forceinline__ void headtail_wide_rule(const DevGrammar& g, int32_t r, uint64_t* len, int32_t* head,
+                                                   int32_t* tail) {
   const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
   uint64_t L = 0;
   int32_t h[kWRow];
@@ -73,15 +70,49 @@ __global__ void k_headtail_wide_level(DevGrammar g, const int32_t* rules, int32_
   }
 }
 
+// One level, a thread per rule; its children (deeper levels) are done.
+__global__ void k_headtail_wide_level(DevGrammar g, const int32_t* rules, int32_t n, uint64_t* len, int32_t* head,
+                                      int32_t* tail) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) headtail_wide_rule(g, rules[i], len, head, tail);
+}
+
+// A run of narrow levels, deepest (d_hi) first, in one workgroup with a
+// workgroup barrier between levels instead of a launch per level.
+constexpr int kWideNarrowThreads = 1024;
+__global__ __launch_bounds__(kWideNarrowThreads) void k_headtail_wide_narrow(DevGrammar g, int32_t d_lo, int32_t d_hi,
+                                                                             uint64_t* len, int32_t* head,
+                                                                             int32_t* tail) {
+  for (int32_t d = d_hi; d >= d_lo; --d) {
+    const int32_t lo = g.level_off[d], hi = g.level_off[d + 1];
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kWideNarrowThreads)
+      headtail_wide_rule(g, g.level_rule[i], len, head, tail);
+    __syncthreads();  // the next level reads what this one wrote
+  }
+}
+
 hipError_t launch_headtail_wide(const DevGrammar& g, const int32_t* level_off_host, int32_t depth, uint64_t* len,
                                 int32_t* head, int32_t* tail, hipStream_t s) {
-  for (int32_t d = depth; d >= 1; --d) {
+  for (int32_t d = depth; d >= 1;) {
     const int32_t lo = level_off_host[d], hi = level_off_host[d + 1];
-    if (hi <= lo) continue;
-    k_headtail_wide_level<<<(unsigned)((hi - lo + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, hi - lo, len, head,
-                                                                           tail);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (hi - lo <= kWideNarrowThreads) {
+      int32_t d_lo = d;  // the run of narrow levels from d upwards
+      while (d_lo > 1 && level_off_host[d_lo] - level_off_host[d_lo - 1] <= kWideNarrowThreads) --d_lo;
+      if (d_lo < d) {
+        k_headtail_wide_narrow<<<1, kWideNarrowThreads, 0, s>>>(g, d_lo, d, len, head, tail);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        d = d_lo - 1;
+        continue;
+      }
+    }
+    if (hi > lo) {
+      k_headtail_wide_level<<<(unsigned)((hi - lo + 255) / 256), 256, 0, s>>>(g, g.level_rule + lo, hi - lo, len,
+                                                                             head, tail);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    --d;
   }
   return hipSuccess;
 }

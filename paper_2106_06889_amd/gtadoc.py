@@ -85,6 +85,13 @@ PARAM_LEVEL_LONG_BODY, PARAM_LEVEL_MID_RULES, PARAM_LEVEL_MID_BLOCKS, PARAM_LEVE
 PARAM_FLOW_KEEP, PARAM_FLOW_GROUP, PARAM_FLOW_CHUNK = 10, 11, 12
 PHASES = {"levels": 0, "word_count": 1, "sort": 2, "seq_windows": 3, "tv_tables": 4, "tv_reduce": 5, "load": 6,
           "decompress": 7, "tv_topdown": 8}
+
+
+def timing_mask(*phases: str) -> int:
+    """PARAM_TIMING value that times only the named phases (bit p + 1 per phase p)."""
+    return sum(2 << PHASES[p] for p in set(phases))
+
+
 TV_AUTO, TV_BOTTOM_UP, TV_TOP_DOWN = 0, 1, 2
 (QUERY_WORD_COUNT, QUERY_TERM_VECTOR, QUERY_SEQUENCE_COUNT, QUERY_INVERTED_INDEX,
  QUERY_RANKED_INVERTED_INDEX) = 1, 2, 3, 4, 5
@@ -110,6 +117,21 @@ def lib() -> ctypes.CDLL:
             fn.restype = ctypes.c_char_p if name == "gtadoc_last_error" else ctypes.c_int
         _lib = l
     return _lib
+
+
+def unload():
+    """Unloads libgtadoc.so once every context and handle is released: its
+    HIP code objects are unregistered now, while the runtime (and any
+    profiler attached to it) is fully up, instead of by the exit-time
+    destructors after a profiler has finalized. Nothing may call into the
+    library afterwards (a later lib() loads it again)."""
+    global _lib
+    if _lib is None:
+        return
+    import _ctypes
+    handle = _lib._handle
+    _lib = None
+    _ctypes.dlclose(handle)
 
 
 def _check(rc: int):

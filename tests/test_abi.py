@@ -34,3 +34,13 @@ def test_library_exports_every_declared_symbol():
 def test_binding_covers_every_declared_symbol():
     from paper_2106_06889_amd import gtadoc
     assert sorted(gtadoc.EXPORTS) == declared()
+
+
+def test_timing_mask_bits():
+    """PARAM_TIMING masks: bit p + 1 per phase p; 1 stays 'every phase'."""
+    import paper_2106_06889_amd as gt
+    assert gt.timing_mask("levels") == 2
+    assert gt.timing_mask("tv_tables", "tv_reduce") == (2 << gt.PHASES["tv_tables"]) | (2 << gt.PHASES["tv_reduce"])
+    assert gt.timing_mask() == 0
+    assert gt.timing_mask("sort", "sort") == 2 << gt.PHASES["sort"]
+    assert all(gt.timing_mask(p) != 1 for p in gt.PHASES)

@@ -332,3 +332,41 @@ def test_heavy_rule_weight(ctx):
             plan.close()
     finally:
         G.free()
+
+
+def test_timing_mask_and_order_across_streams(ctx):
+    """A timing mask times only the phases it names; a call on another stream
+    is ordered after the previous call's work (the sort on stream 2 reads the
+    counts the word count on stream 1 writes)."""
+    import torch
+    import paper_2106_06889_amd as gt
+    c = synth.random_corpus(29, 2, 60000, 3000)
+    g = synth.compress(c.tokens, c.file_off, c.vocab)
+    want = oracle.traverse_word_count(g)
+    wid, wcnt = oracle.sort_counts(want)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for ph in gt.PHASES:
+        ctx.phase_time(ph, reset=True)
+    ctx.set_param(gt.PARAM_TIMING, gt.timing_mask("levels", "sort"))
+    try:
+        assert ctx.get_param(gt.PARAM_TIMING) == gt.timing_mask("levels", "sort")
+        G = ctx.load(g.rule_off, g.sym, g.file_off, g.vocab, stream=s1)
+        out = torch.empty(g.vocab, dtype=torch.int64, device=ctx.device)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            G.word_count(out, stream=s1)
+            ids, cnt, num = G.sort(out, stream=s2)
+            s2.synchronize()
+            k = int(num.item())
+            assert k == len(wid)
+            assert np.array_equal(ids[:k].cpu().numpy().view(np.uint32), wid)
+            assert np.array_equal(gt.to_u64(cnt[:k]), wcnt)
+        s1.synchronize()
+        assert np.array_equal(gt.to_u64(out), want)
+        counts = {ph: ctx.phase_time(ph, reset=True)[1] for ph in ("levels", "word_count", "sort", "load")}
+        assert counts == {"levels": 1, "word_count": 0, "sort": 3, "load": 0}, counts
+        G.free()
+    finally:
+        ctx.set_param(gt.PARAM_TIMING, 0)
+    with pytest.raises(gt.GtadocError):
+        ctx.set_param(gt.PARAM_TIMING, 2 << len(gt.PHASES))
