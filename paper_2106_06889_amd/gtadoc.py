@@ -119,21 +119,6 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
-def unload():
-    """Unloads libgtadoc.so once every context and handle is released: its
-    HIP code objects are unregistered now, while the runtime (and any
-    profiler attached to it) is fully up, instead of by the exit-time
-    destructors after a profiler has finalized. Nothing may call into the
-    library afterwards (a later lib() loads it again)."""
-    global _lib
-    if _lib is None:
-        return
-    import _ctypes
-    handle = _lib._handle
-    _lib = None
-    _ctypes.dlclose(handle)
-
-
 def _check(rc: int):
     if rc != OK:
         raise GtadocError(rc, lib().gtadoc_last_error().decode())
