@@ -40,36 +40,73 @@ constexpr uint64_t kEmptyKey = ~0ull;  // never a valid packed n-gram
 constexpr int kHT = 3;
 constexpr int kHTRow = 4;
 
+// The rule's length sums its pieces (a word, or a child's length) with the
+// loads of 8 pieces in flight at a time; its first kHT words come from its
+// first kHT pieces and its last kHT words from its last kHT pieces (every
+// piece is at least one word), loaded together, so a rule costs a few
+// dependent memory round trips instead of two per piece.
 __device__ __forceinline__ void headtail_rule(const DevGrammar& g, int32_t r, uint64_t* len, int32_t* head,
                                               int32_t* tail) {
+  constexpr int kBatch = 8;
   const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  const int64_t np = b - a;
+  int32_t fs[kHT], ls[kHT];  // first pieces in order; last pieces from the end
+  v4i32 fr[kHT], lr[kHT];    // their head / tail rows (children only)
+  uint64_t fl[kHT], ll[kHT];
+#pragma unroll
+  for (int k = 0; k < kHT; ++k) {
+    fs[k] = k < np ? g.sym[a + k] : 0;
+    ls[k] = k < np ? g.sym[b - 1 - k] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kHT; ++k) {
+    fl[k] = 1, ll[k] = 1;
+    if (k < np && fs[k] < 0) {
+      const int64_t c = -(int64_t)fs[k];
+      fl[k] = len[c];
+      fr[k] = *reinterpret_cast<const v4i32*>(head + kHTRow * c);
+    }
+    if (k < np && ls[k] < 0) {
+      const int64_t c = -(int64_t)ls[k];
+      ll[k] = len[c];
+      lr[k] = *reinterpret_cast<const v4i32*>(tail + kHTRow * c);
+    }
+  }
   uint64_t L = 0;
+  for (int64_t q0 = a; q0 < b; q0 += kBatch) {
+    int32_t sv[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) sv[k] = q0 + k < b ? g.sym[q0 + k] : 0;
+    uint64_t lc[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) lc[k] = q0 + k >= b ? 0 : (sv[k] >= 0 ? 1 : len[-(int64_t)sv[k]]);
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) L += lc[k];
+  }
   int32_t h[kHT] = {-1, -1, -1};
   int hc = 0;
-  for (int64_t q = a; q < b; ++q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      ++L;
-      if (hc < kHT) h[hc++] = s;
+#pragma unroll
+  for (int k = 0; k < kHT; ++k) {
+    if (k >= np) break;
+    if (fs[k] >= 0) {
+      if (hc < kHT) h[hc++] = fs[k];
     } else {
-      const int64_t c = -(int64_t)s;
-      const uint64_t lc = len[c];
-      L += lc;
-      const int take = lc < kHT ? (int)lc : kHT;
-      for (int j = 0; j < take && hc < kHT; ++j) h[hc++] = head[kHTRow * c + j];
+      const int take = fl[k] < kHT ? (int)fl[k] : kHT;
+      const int32_t row[4] = {fr[k].x, fr[k].y, fr[k].z, fr[k].w};
+      for (int j = 0; j < take && hc < kHT; ++j) h[hc++] = row[j];
     }
   }
   int32_t tr[kHT] = {-1, -1, -1};  // collected from the right: tr[0] is the last word
   int tc = 0;
-  for (int64_t q = b - 1; q >= a && tc < kHT; --q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      tr[tc++] = s;
+#pragma unroll
+  for (int k = 0; k < kHT; ++k) {
+    if (k >= np) break;
+    if (ls[k] >= 0) {
+      if (tc < kHT) tr[tc++] = ls[k];
     } else {
-      const int64_t c = -(int64_t)s;
-      const uint64_t lc = len[c];
-      const int take = lc < kHT ? (int)lc : kHT;
-      for (int j = take - 1; j >= 0 && tc < kHT; --j) tr[tc++] = tail[kHTRow * c + j];
+      const int take = ll[k] < kHT ? (int)ll[k] : kHT;
+      const int32_t row[4] = {lr[k].x, lr[k].y, lr[k].z, lr[k].w};
+      for (int j = take - 1; j >= 0 && tc < kHT; --j) tr[tc++] = row[j];
     }
   }
   len[r] = L;

@@ -28,37 +28,61 @@ constexpr int kWHT = 7;       // head/tail words kept per rule (n - 1 <= 7)
 constexpr int kWRow = 8;      // row stride (32 bytes)
 constexpr uint64_t kWEmpty = ~0ull;
 
+// Length with the loads of 8 pieces in flight at a time; the first (last)
+// kWHT words come from the first (last) kWHT pieces, loaded together.
 __device__ __forceinline__ void headtail_wide_rule(const DevGrammar& g, int32_t r, uint64_t* len, int32_t* head,
                                                    int32_t* tail) {
+  constexpr int kBatch = 8;
   const int64_t a = g.rule_off[r], b = g.rule_off[r + 1];
+  const int64_t np = b - a;
   uint64_t L = 0;
+  for (int64_t q0 = a; q0 < b; q0 += kBatch) {
+    int32_t sv[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) sv[k] = q0 + k < b ? g.sym[q0 + k] : 0;
+    uint64_t lc[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) lc[k] = q0 + k >= b ? 0 : (sv[k] >= 0 ? 1 : len[-(int64_t)sv[k]]);
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) L += lc[k];
+  }
   int32_t h[kWRow];
   for (int x = 0; x < kWRow; ++x) h[x] = -1;
   int hc = 0;
-  for (int64_t q = a; q < b; ++q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      ++L;
-      if (hc < kWHT) h[hc++] = s;
-    } else {
-      const int64_t c = -(int64_t)s;
-      const uint64_t lc = len[c];
-      L += lc;
-      const int take = lc < kWHT ? (int)lc : kWHT;
-      for (int j = 0; j < take && hc < kWHT; ++j) h[hc++] = head[kWRow * c + j];
+  {
+    int32_t ps[kWHT];
+    uint64_t pl[kWHT];
+#pragma unroll
+    for (int k = 0; k < kWHT; ++k) ps[k] = k < np ? g.sym[a + k] : 0;
+#pragma unroll
+    for (int k = 0; k < kWHT; ++k) pl[k] = k < np && ps[k] < 0 ? len[-(int64_t)ps[k]] : 1;
+    for (int k = 0; k < kWHT && k < np && hc < kWHT; ++k) {
+      if (ps[k] >= 0) {
+        h[hc++] = ps[k];
+      } else {
+        const int64_t c = -(int64_t)ps[k];
+        const int take = pl[k] < kWHT ? (int)pl[k] : kWHT;
+        for (int j = 0; j < take && hc < kWHT; ++j) h[hc++] = head[kWRow * c + j];
+      }
     }
   }
   int32_t tr[kWHT];  // collected from the right: tr[0] is the last word
   int tc = 0;
-  for (int64_t q = b - 1; q >= a && tc < kWHT; --q) {
-    const int32_t s = g.sym[q];
-    if (s >= 0) {
-      tr[tc++] = s;
-    } else {
-      const int64_t c = -(int64_t)s;
-      const uint64_t lc = len[c];
-      const int take = lc < kWHT ? (int)lc : kWHT;
-      for (int j = take - 1; j >= 0 && tc < kWHT; --j) tr[tc++] = tail[kWRow * c + j];
+  {
+    int32_t ps[kWHT];
+    uint64_t pl[kWHT];
+#pragma unroll
+    for (int k = 0; k < kWHT; ++k) ps[k] = k < np ? g.sym[b - 1 - k] : 0;
+#pragma unroll
+    for (int k = 0; k < kWHT; ++k) pl[k] = k < np && ps[k] < 0 ? len[-(int64_t)ps[k]] : 1;
+    for (int k = 0; k < kWHT && k < np && tc < kWHT; ++k) {
+      if (ps[k] >= 0) {
+        tr[tc++] = ps[k];
+      } else {
+        const int64_t c = -(int64_t)ps[k];
+        const int take = pl[k] < kWHT ? (int)pl[k] : kWHT;
+        for (int j = take - 1; j >= 0 && tc < kWHT; --j) tr[tc++] = tail[kWRow * c + j];
+      }
     }
   }
   len[r] = L;
