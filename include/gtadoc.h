@@ -23,10 +23,13 @@
  *    them.
  *  - A context is driven by one host thread at a time. Calls on different
  *    streams are ordered by the context: a call on another stream than the
- *    previous call's records an event on that stream and waits for it, so
- *    arena memory released by one call is never reused while another stream
- *    still reads it (calls on one stream are ordered by the stream and
- *    record no event). gtadoc_ctx_destroy waits for the whole device.
+ *    previous call's waits for an event recorded after the previous call's
+ *    work, so arena memory released by one call is never reused while
+ *    another stream still reads it. A call on a caller-created stream
+ *    records that event when it ends (the stream may be destroyed later);
+ *    consecutive calls on the null stream record none (the next call on
+ *    another stream records it on the null stream). gtadoc_ctx_destroy waits
+ *    for the whole device.
  *
  * Grammar encoding (CSR, identical for host and device inputs):
  *   rule_off int64[num_rules + 1]  body(r) = sym[rule_off[r] .. rule_off[r+1]);

@@ -136,7 +136,7 @@ struct gtadoc_ctx_s {
   char* base = nullptr;
   Arena arena;
   int device = 0;
-  hipEvent_t done = nullptr;     // recorded on `last` when a call comes on another stream
+  hipEvent_t done = nullptr;     // after the most recent call's work (see Call)
   hipStream_t last = nullptr;    // stream of the most recent call
   bool has_done = false;         // there was such a call
   char* pinned = nullptr;        // small pinned host buffer for read-backs
@@ -212,10 +212,13 @@ namespace {
 // Orders a call after the previous call on the same context and owns the
 // call's scratch, which goes back to the arena when the call returns (later
 // calls are ordered after this one's work, so the reuse is safe). Calls on
-// one stream are ordered by the stream; a call on another stream records
-// an event on the previous call's stream when it begins and waits for it,
-// so no event is recorded between calls on one stream (each would leave
-// the GPU idle for a few microseconds).
+// one stream are ordered by the stream; a call on another stream waits for
+// an event recorded after the previous call. A call on a stream the caller
+// created records that event when it ends (the stream may be destroyed
+// afterwards); a call on the null stream, which cannot be destroyed, leaves
+// it to the next call on another stream, so back-to-back calls on the null
+// stream record no event (each would leave the GPU idle for a few
+// microseconds).
 class Call {
  public:
   Call(gtadoc_ctx ctx, void* stream) : ctx_(ctx), s_(static_cast<hipStream_t>(stream)) {}
@@ -228,7 +231,7 @@ class Call {
   int begin() {
     if (hipSetDevice(ctx_->device) != hipSuccess) return fail(GTADOC_ERR_HIP, "hipSetDevice failed");
     if (!defer_ && ctx_->has_done && ctx_->last != s_) {
-      HIP_TRY(hipEventRecord(ctx_->done, ctx_->last));
+      if (ctx_->last == nullptr) HIP_TRY(hipEventRecord(ctx_->done, nullptr));
       HIP_TRY(hipStreamWaitEvent(s_, ctx_->done, 0));
     }
     return GTADOC_OK;
@@ -239,6 +242,7 @@ class Call {
       return;
     }
     for (const Block& b : scratch_) ctx_->arena.release(b);
+    if (s_ != nullptr) (void)hipEventRecord(ctx_->done, s_);
     ctx_->last = s_;
     ctx_->has_done = true;
   }

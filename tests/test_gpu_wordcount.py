@@ -370,3 +370,43 @@ def test_timing_mask_and_order_across_streams(ctx):
         ctx.set_param(gt.PARAM_TIMING, 0)
     with pytest.raises(gt.GtadocError):
         ctx.set_param(gt.PARAM_TIMING, 2 << len(gt.PHASES))
+
+
+def test_call_after_previous_stream_destroyed():
+    """A call on a new stream after the previous call's stream was destroyed
+    still runs (ordered by a device-wide wait) and is exact. Runs in a child
+    process of its own, so a failure cannot take the test session down."""
+    import subprocess
+    import sys
+    script = r"""
+import ctypes, sys
+import numpy as np, torch
+sys.path.insert(0, %r)
+import oracle, synth
+import paper_2106_06889_amd as gt
+hip = ctypes.CDLL("libamdhip64.so")
+c = synth.random_corpus(31, 1, 20000, 500)
+g = synth.compress(c.tokens, c.file_off, c.vocab)
+want = oracle.traverse_word_count(g)
+ctx = gt.Context(64 << 20)
+lib = gt.lib()
+s = ctypes.c_void_p()
+assert hip.hipStreamCreate(ctypes.byref(s)) == 0
+h = ctypes.c_void_p()
+ro, sy, fo = np.ascontiguousarray(g.rule_off), np.ascontiguousarray(g.sym), np.ascontiguousarray(g.file_off)
+gt.gtadoc._check(lib.gtadoc_load_grammar(ctx.handle, ro.ctypes.data, len(ro) - 1, sy.ctypes.data, len(sy),
+                                         fo.ctypes.data, len(fo) - 1, g.vocab, gt.gtadoc.IN_HOST, s, ctypes.byref(h)))
+out1 = torch.empty(g.vocab, dtype=torch.int64, device="cuda")
+gt.gtadoc._check(lib.gtadoc_word_count(h, out1.data_ptr(), s))
+assert hip.hipStreamSynchronize(s) == 0
+assert hip.hipStreamDestroy(s) == 0
+out2 = torch.empty(g.vocab, dtype=torch.int64, device="cuda")
+gt.gtadoc._check(lib.gtadoc_word_count(h, out2.data_ptr(), torch.cuda.current_stream().cuda_stream))
+torch.cuda.synchronize()
+assert np.array_equal(gt.to_u64(out1), want) and np.array_equal(gt.to_u64(out2), want)
+gt.gtadoc._check(lib.gtadoc_free_grammar(h))
+ctx.close()
+print("ok")
+""" % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
