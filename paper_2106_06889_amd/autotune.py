@@ -32,7 +32,7 @@ CANDIDATES = {
     gt.PARAM_BATCH_BLOCKS_PER_CU: [1, 2, 4, 8],
     gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
 }
-DEFAULTS = {gt.PARAM_BATCH_BLOCKS_PER_CU: 4, gt.PARAM_WC_CHUNK: 32768}
+DEFAULTS = {gt.PARAM_BATCH_BLOCKS_PER_CU: 4, gt.PARAM_WC_CHUNK: 16384}
 NAMES = {gt.PARAM_BATCH_BLOCKS_PER_CU: "batch_blocks_per_cu", gt.PARAM_WC_CHUNK: "wc_chunk",
          gt.PARAM_LEVEL_WIDE: "level_wide", gt.PARAM_LEVEL_LONG_BODY: "level_long_body",
          gt.PARAM_LEVEL_MID_RULES: "level_mid_rules", gt.PARAM_LEVEL_MID_BLOCKS: "level_mid_blocks",
@@ -49,7 +49,7 @@ LOAD_CANDIDATES = {
     gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
 }
 LOAD_DEFAULTS = {gt.PARAM_LEVEL_WIDE: 262144, gt.PARAM_LEVEL_MID_RULES: 49152, gt.PARAM_LEVEL_MID_BLOCKS: 32,
-                 gt.PARAM_LEVEL_TAIL_RULES: 1024, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 32768}
+                 gt.PARAM_LEVEL_TAIL_RULES: 1024, gt.PARAM_LEVEL_LONG_BODY: 32, gt.PARAM_WC_CHUNK: 16384}
 # the load by the dataflow walk (no levels) and the word count
 FLOW_CANDIDATES = {
     gt.PARAM_FLOW_CHUNK: [64, 128, 256, 512],
@@ -57,7 +57,7 @@ FLOW_CANDIDATES = {
     gt.PARAM_WC_CHUNK: [8192, 16384, 32768, 65536],
 }
 FLOW_DEFAULTS = {gt.PARAM_FLOW_CHUNK: 128, gt.PARAM_FLOW_GROUP: 1024, gt.PARAM_FLOW_KEEP: 4096,
-                 gt.PARAM_WC_CHUNK: 32768}
+                 gt.PARAM_WC_CHUNK: 16384}
 
 
 def arch() -> str:

@@ -140,7 +140,7 @@ struct gtadoc_ctx_s {
   hipStream_t last = nullptr;    // stream of the most recent call
   bool has_done = false;         // there was such a call
   char* pinned = nullptr;        // small pinned host buffer for read-backs
-  int64_t wc_chunk = 32 * 1024;  // word-count reduce chunk (tunable)
+  int64_t wc_chunk = 16 * 1024;  // word-count reduce chunk (tunable)
   int64_t batch_blocks_per_cu = 4;
   int64_t batch_graph = 0;
   int64_t param_epoch = 0;       // bumped on every parameter change (invalidates captured graphs)

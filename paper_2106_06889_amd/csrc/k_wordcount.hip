@@ -191,10 +191,12 @@ __global__ __launch_bounds__(kWcScatterThreads) void k_wc_scatter(DevGrammar g, 
 // frequencies, so whole buckets per workgroup would leave a few workgroups
 // with most of the work). A workgroup sums each bucket segment of its chunk
 // in LDS -- kWcCopies copies of the bucket's table, wave w using copy
-// w % kWcCopies, so one frequent word's adds spread over several addresses --
-// then adds the nonzero sums to the (zeroed) count array with coalesced
-// global atomics.
-constexpr int kWcCopies = 4;
+// w % kWcCopies -- then adds the nonzero sums to the (zeroed) count array
+// with coalesced global atomics. One copy: spreading a frequent word's adds
+// over four copies (128 KB of LDS, one workgroup per CU) took 176 us for the
+// pass on the 10^8-token corpus, one copy (32 KB, two workgroups per CU)
+// 162 us; same-address LDS conflicts cost less than the lost occupancy.
+constexpr int kWcCopies = 1;
 constexpr int kWcThreads = 1024;
 
 // First bucket whose range [start(b), start(b+1)) holds entry i; start(b) =
