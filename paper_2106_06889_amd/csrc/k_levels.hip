@@ -27,14 +27,17 @@
 namespace gt {
 
 // Level 1 = the rules with no pending in-edge (used only by the root, or not
-// at all), compacted in rule-id order: a count per block of kBlockSyms rules,
-// an exclusive scan, then every block writes its rules at its offset.
+// at all), compacted in rule-id order: a count per block of kRadixTile
+// rules, an exclusive scan, then every block writes its rules at its offset.
+// Rule i0 + k * 256 + thread (k < 16) of a block: the lanes of a wave read
+// consecutive words, and the output keeps rule-id order by ranking the
+// rules of each (step k, wave) with a ballot.
 __global__ __launch_bounds__(256) void k_zero_count(const uint64_t* pw, int64_t R, uint32_t* cnt) {
-  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const int64_t r = i0 + k;
+    const int64_t r = i0 + k * 256;
     if (r >= 1 && r < R && (pw[r] & kPendMask) == 0) ++c;
   }
   __shared__ uint32_t lds[4];
@@ -56,23 +59,36 @@ __global__ __launch_bounds__(256) void k_zero_write(const uint64_t* pw, int64_t 
     fs->ticket = 0;
     fs->nspill = 0;
   }
-  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x * 16;
-  uint32_t c = 0;
-  bool z[16];
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t i0 = (int64_t)blockIdx.x * kRadixTile + threadIdx.x;
+  __shared__ uint32_t start[16][4];  // per (step, wave): count, then first output position
+  uint64_t w[16];
+  uint64_t zm[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const int64_t r = i0 + k;
-    z[k] = r >= 1 && r < R && (pw[r] & kPendMask) == 0;
-    c += z[k];
+    const int64_t r = i0 + k * 256;
+    w[k] = r < R ? pw[r] : 1u;
+    zm[k] = __ballot(r >= 1 && r < R && (w[k] & kPendMask) == 0);
+    if (lane == 0) start[k][wave] = (uint32_t)__popcll(zm[k]);
   }
-  __shared__ uint32_t lds[4];
-  uint32_t total;
-  uint32_t pos = off[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+  __syncthreads();
+  if (wave == 0) {  // exclusive scan of the 64 counts in (k, wave) order = rule-id order
+    const uint32_t v = start[lane >> 2][lane & 3];
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    start[lane >> 2][lane & 3] = off[blockIdx.x] + x - v;
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (z[k]) {
-      if (qw) qw[pos] = pw[i0 + k] >> kPendBits;
-      out[pos++] = (int32_t)(i0 + k);
+    if ((zm[k] >> lane) & 1) {
+      const uint32_t pos = start[k][wave] + (uint32_t)__popcll(zm[k] & lanes_below());
+      if (qw) qw[pos] = w[k] >> kPendBits;
+      out[pos] = (int32_t)(i0 + k * 256);
     }
 }
 
