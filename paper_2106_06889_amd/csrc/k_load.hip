@@ -398,15 +398,17 @@ __device__ __forceinline__ void scan2_chunk(const Scan2& q, uint32_t*& arr, int6
   else arr = q.b, n = q.nb, chunk = blockIdx.x - q.ca;
 }
 
+// A chunk of kRadixTile entries is read as element i0 + k * 256 + thread
+// (k < 16): the lanes of a wave read consecutive words.
 __global__ __launch_bounds__(256) void k_scan2_sums(Scan2 q, uint32_t* sums) {
   uint32_t* arr;
   int64_t n, chunk;
   scan2_chunk(q, arr, n, chunk);
-  const int64_t i0 = chunk * kRadixTile + threadIdx.x * 16;
+  const int64_t i0 = chunk * kRadixTile + threadIdx.x;
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (i0 + k < n) c += arr[i0 + k];
+    if (i0 + k * 256 < n) c += arr[i0 + k * 256];
   __shared__ uint32_t lds[4];
   uint32_t total;
   block_exclusive_scan_256(c, lds, &total);
@@ -449,26 +451,44 @@ __global__ __launch_bounds__(1024) void k_scan2_mid(uint32_t* sums, int64_t ca, 
   block_scan_inplace(sums + ca, cb, tb, wsum);
 }
 
+// Element order within the chunk is (step k, wave, lane): each wave scans
+// its 64 values of every step, then one wave scans the 64 (step, wave)
+// totals, which places every value at its element-order prefix.
 __global__ __launch_bounds__(256) void k_scan2_apply(Scan2 q, const uint32_t* sums) {
   uint32_t* arr;
   int64_t n, chunk;
   scan2_chunk(q, arr, n, chunk);
-  const int64_t i0 = chunk * kRadixTile + threadIdx.x * 16;
-  uint32_t v[16], c = 0;
+  const int64_t i0 = chunk * kRadixTile + threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  __shared__ uint32_t start[16][4];  // per (step, wave): total, then exclusive prefix
+  uint32_t v[16], ex[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    v[k] = (i0 + k < n) ? arr[i0 + k] : 0u;
-    c += v[k];
+    v[k] = (i0 + k * 256 < n) ? arr[i0 + k * 256] : 0u;
+    uint32_t x = v[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    ex[k] = x - v[k];
+    if (lane == 63) start[k][wave] = x;
   }
-  __shared__ uint32_t lds[4];
-  uint32_t total;
-  uint32_t run = sums[blockIdx.x] + block_exclusive_scan_256(c, lds, &total);
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t t = start[lane >> 2][lane & 3];
+    uint32_t x = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    start[lane >> 2][lane & 3] = sums[blockIdx.x] + x - t;
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 16; ++k)
-    if (i0 + k < n) {
-      arr[i0 + k] = run;
-      run += v[k];
-    }
+    if (i0 + k * 256 < n) arr[i0 + k * 256] = start[k][wave] + ex[k];
 }
 
 hipError_t launch_scan_offsets2(uint32_t* a, int64_t na, int64_t* ta, uint32_t* b, int64_t nb, int64_t* tb,
