@@ -77,12 +77,15 @@ class Server:
     max_batch, one per grammar per step, word symbols within the plan) and
     term-vector / bigram queries while the arena's free bytes cover their
     footprint (gtadoc_query_bytes, measured by the library per grammar and
-    kind), at most max_other per step. The step is one mixed batch
+    kind), at most max_other per step. A step of a single query calls its
+    own entry point. The step is one mixed batch
     (gtadoc_batch_submit): the word counts as one batched launch sequence,
     the other queries on the plan's own streams, their kernels overlapping on
     the device. Two plans alternate, so a step is admitted and queued while
     the previous one is still on the GPU; queries that arrive meanwhile join
-    the next step."""
+    the next step. The word counts of a step are submitted first and
+    complete at their own event, so they do not wait for the step's term
+    vectors and bigram counts."""
 
     def __init__(self, ctx: gt.Context, grammars: list, max_batch: int = 64, max_entries: int | None = None,
                  keep_results: bool = False, max_other: int = 8, plans: int = 2):
@@ -146,8 +149,8 @@ class Server:
         # the stream has passed them
         self.stream.synchronize()
 
-    def _finish(self, step, now: float, recs: dict):
-        ev, qs, got = step
+    def _finish(self, group, now: float, recs: dict):
+        _, qs, got = group
         for q, r in zip(qs, got):
             rec = recs[q.qid]
             rec.finish = now
@@ -168,7 +171,7 @@ class Server:
         recs = {q.qid: Record(q.qid, q.kind, q.grammar, q.arrival) for q in pending}
         queue: deque[Query] = deque()
         i, n = 0, len(pending)
-        inflight: deque = deque()  # (event, queries, results), oldest first
+        inflight: deque = deque()  # steps, oldest first: lists of (event, queries, results) groups
         turn = 0
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0  # noqa: E731
@@ -177,8 +180,14 @@ class Server:
             while i < n and (not realtime or pending[i].arrival <= now):
                 queue.append(pending[i])
                 i += 1
-            while inflight and inflight[0][0].query():
-                self._finish(inflight.popleft(), clock(), recs)
+            while inflight:
+                groups = inflight[0]
+                for gr in [gr for gr in groups if gr[0].query()]:
+                    self._finish(gr, clock(), recs)
+                    groups.remove(gr)
+                if groups:
+                    break
+                inflight.popleft()
             if queue and len(inflight) < len(self.plans):
                 # admit: word counts into the batch, the others by arena headroom
                 batch, entries, rest, others = [], 0, deque(), []
@@ -208,28 +217,54 @@ class Server:
                         continue  # wait for memory to come back
                     others.append(queue.popleft())  # too big for any step with others: alone
                 start = clock()
-                step_q = batch + others
                 slot = turn % len(self.plans)
                 outs = self.outs[slot]
-                spec = []
-                for q in step_q:
-                    G = self.grammars[q.grammar]
-                    if q.kind == "wc":
-                        if q.grammar not in outs:
-                            outs[q.grammar] = torch.empty(G.vocab, dtype=torch.int64, device=self.ctx.device)
-                        spec.append({"grammar": G, "kind": gt.QUERY_WORD_COUNT, "counts": outs[q.grammar]})
-                    elif q.kind == "tv":
-                        spec.append({"grammar": G, "kind": gt.QUERY_TERM_VECTOR})
-                    else:
-                        spec.append({"grammar": G, "kind": gt.QUERY_SEQUENCE_COUNT, "n": 2})
+                groups = []
+                if len(batch) + len(others) == 1:
+                    # a step of one query runs it by its own entry point, as
+                    # the plain loop does: the batch machinery pays off only
+                    # when several queries share a step
+                    q = (batch + others)[0]
                     recs[q.qid].start = start
-                got = self.plans[slot].submit(spec)
+                    G = self.grammars[q.grammar]
+                    try:
+                        if q.kind == "wc":
+                            if q.grammar not in outs:
+                                outs[q.grammar] = torch.empty(G.vocab, dtype=torch.int64, device=self.ctx.device)
+                            r = G.word_count(outs[q.grammar])
+                        elif q.kind == "tv":
+                            r = G.term_vector()
+                        else:
+                            r = G.sequence_count(2)
+                    except gt.GtadocError as e:
+                        r = e
+                    ev = torch.cuda.Event()
+                    ev.record(self.stream)
+                    groups.append((ev, [q], [r]))
+                    batch, others = [], []
+                for qs in (batch, others):  # the word counts first, at their own event
+                    if not qs:
+                        continue
+                    spec = []
+                    for q in qs:
+                        G = self.grammars[q.grammar]
+                        if q.kind == "wc":
+                            if q.grammar not in outs:
+                                outs[q.grammar] = torch.empty(G.vocab, dtype=torch.int64, device=self.ctx.device)
+                            spec.append({"grammar": G, "kind": gt.QUERY_WORD_COUNT, "counts": outs[q.grammar]})
+                        elif q.kind == "tv":
+                            spec.append({"grammar": G, "kind": gt.QUERY_TERM_VECTOR})
+                        else:
+                            spec.append({"grammar": G, "kind": gt.QUERY_SEQUENCE_COUNT, "n": 2})
+                        recs[q.qid].start = start
+                    got = self.plans[slot].submit(spec)
+                    ev = torch.cuda.Event()
+                    ev.record(self.stream)
+                    groups.append((ev, qs, got))
                 turn += 1
-                ev = torch.cuda.Event()
-                ev.record(self.stream)
-                inflight.append((ev, step_q, got))
+                inflight.append(groups)
             elif inflight:
-                time.sleep(2e-5)
+                pass  # poll the oldest step's events again (a sleep would add its timer slack to the latency)
             elif i < n:
                 # idle until the next arrival
                 wait = pending[i].arrival - clock()
