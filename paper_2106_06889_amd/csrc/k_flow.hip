@@ -27,7 +27,9 @@
 // back to their rule by binary search in LDS), 8 at a time, issuing all 8
 // atomics before it looks at any result. A round costs about the same for a
 // 2-symbol body and a 300-symbol one, and neighbouring threads read
-// neighbouring symbols.
+// neighbouring symbols. At the end of the walk, where rounds hold a few
+// rules of long chains of deep rules, a thread walks a short rule its atomic
+// readied at once, and so down the chain, instead of a round per link.
 //
 // Work sharing. A round takes rules from the workgroup's LDS ring first,
 // then from a held range of a global queue. The queue starts with level 1
@@ -54,6 +56,13 @@
 namespace gt {
 
 constexpr uint32_t kFlowSpinLimit = 1u << 21;
+// Rounds of at most kFlowContRound rules (the end of the walk, where the
+// deepest rules form chains) let a thread walk a rule it readied at once:
+// bodies of at most kFlowContBody symbols, at most kFlowContLinks links in a
+// row; the rest goes to the ring.
+constexpr int kFlowContRound = 32;
+constexpr int64_t kFlowContBody = 16;
+constexpr int kFlowContLinks = 256;
 
 template <int kT>
 struct FlowLds {
@@ -251,7 +260,7 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
     L.n0 = (uint32_t)((L.n1 + chunk0 - 1) / chunk0);
   }
   uint64_t tokens = 0;
-  int64_t walked = 0;  // thread 0
+  int64_t walked = 0;  // rules walked: the rounds' (thread 0) and the chains walked in place
   __syncthreads();
   for (;;) {
     if (t == 0) flow_decide(L, fs, fb, status);
@@ -286,6 +295,10 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
     if (t == 0) L.roff[n] = total;
     __syncthreads();
     // the round's symbols, 8 per thread at a time
+    const bool tail = n <= kFlowContRound;
+    bool has_cont = false;  // a rule this thread readied and walks itself (tail rounds)
+    int32_t cc = 0;
+    uint64_t cw = 0;
     int step = 1;
     while (step * 2 <= n) step *= 2;
     for (uint32_t p0 = 0; p0 < total; p0 += 8u * kT) {
@@ -327,8 +340,60 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         if (ref[k] && (old[k] >> kPendBits) + wr[k] >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
-        flow_push(L, fs, fb, status, ref[k] && (old[k] & kPendMask) == 1, cs[k], (old[k] >> kPendBits) + wr[k]);
+        const bool ready = ref[k] && (old[k] & kPendMask) == 1;
+        const uint64_t wf = (old[k] >> kPendBits) + wr[k];
+        const bool here = tail && ready && !has_cont;
+        if (here) has_cont = true, cc = cs[k], cw = wf;
+        flow_push(L, fs, fb, status, ready && !here, cs[k], wf);
       }
+    }
+    // Chains in place: the thread walks the rule it kept, then the first
+    // rule that walk readies, and so on, a few memory round trips per link
+    // instead of a round; every other readied rule goes to the ring.
+    int links = 0;
+    while (has_cont) {
+      const int64_t a = g.rule_off[cc];
+      const int64_t e = g.rule_off[cc + 1];
+      if (e - a > kFlowContBody || links >= kFlowContLinks) {
+        flow_push(L, fs, fb, status, true, cc, cw);
+        break;
+      }
+      ++links;
+      ++walked;
+      bool nxt = false;
+      int32_t nc = 0;
+      uint64_t nw = 0;
+      for (int64_t q0 = a; q0 < e; q0 += 8) {
+        int32_t sv[8], ch[8];
+        uint64_t o[8];
+        bool rf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sv[k] = q0 + k < e ? g.sym[q0 + k] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {  // every atomic issued before any result is used
+          rf[k] = false, ch[k] = 0, o[k] = 0;
+          if (q0 + k >= e) continue;
+          if (sv[k] >= 0) {
+            tokens += cw;
+          } else if (-(int64_t)sv[k] < g.R) {
+            ch[k] = (int32_t)(-(int64_t)sv[k]);
+            rf[k] = true;
+            o[k] = flow_retire(g.w, ch[k], cw);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (rf[k] && (o[k] >> kPendBits) + cw >= (1ull << kWeightBits)) atomicOr(status, (uint32_t)ST_PACK);
+          const bool ready = rf[k] && (o[k] & kPendMask) == 1;
+          const uint64_t wf = (o[k] >> kPendBits) + cw;
+          const bool here = ready && !nxt;
+          if (here) nxt = true, nc = ch[k], nw = wf;
+          flow_push(L, fs, fb, status, ready && !here, ch[k], wf);
+        }
+      }
+      has_cont = nxt;
+      cc = nc;
+      cw = nw;
     }
     __syncthreads();
     if (t == 0) {
@@ -383,7 +448,15 @@ __global__ __launch_bounds__(kT) void k_flow(DevGrammar g, LoadCounters* lc, Flo
     uint64_t sum = 0;
     for (int k = 0; k < kT / 64; ++k) sum += L.part[k];
     if (sum) atomicAdd(reinterpret_cast<unsigned long long*>(&lc->tokens), (unsigned long long)sum);
-    if (walked) atomicAdd(&lc->placed, (int32_t)walked);
+  }
+  __syncthreads();
+  const uint64_t nw = wave_sum_u64((uint64_t)walked);
+  if (lane_id() == 0) L.part[t >> 6] = nw;
+  __syncthreads();
+  if (t == 0) {
+    uint64_t sum = 0;
+    for (int k = 0; k < kT / 64; ++k) sum += L.part[k];
+    if (sum) atomicAdd(&lc->placed, (int32_t)sum);
   }
 }
 
