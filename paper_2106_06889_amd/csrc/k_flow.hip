@@ -49,8 +49,9 @@
 // before they are published, since another workgroup may walk them (and
 // subtract them) before the round ends. The rules a round has taken stay
 // counted until it ends, so `live` is zero only when no work is left, and a
-// workgroup waiting on a ticket leaves when it reads zero. Every wait is
-// bounded.
+// workgroup waiting on a ticket leaves when it reads zero. Rules a thread
+// walks in place are never counted: the round's own rules keep `live` above
+// zero while it walks them. Every wait is bounded.
 #include "device.h"
 
 namespace gt {
