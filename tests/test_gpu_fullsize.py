@@ -2,8 +2,8 @@
 oracle's traversal, which is fast in C): word count + sort on the 100M-token
 single-file corpus, bigram and trigram counts on the 20M-token nested-repeat
 corpus; term vector + inverted index + ranked inverted index on the
-4,000-file corpus (sampled files against the uncompressed text, properties
-on every file)."""
+4,000-file corpus, and the term vector by both traversals on the 4-file
+corpus (every file's row against the uncompressed text)."""
 import numpy as np
 import pytest
 
@@ -153,3 +153,48 @@ def test_seq_20m_fourgrams_wide_full(ctx):
     want = oracle.traverse_sequence_count_wide(g, 4)
     assert all(np.array_equal(a, b) for a, b in zip(got, want))
     assert int(got[2].sum()) == T - 3
+
+
+@pytest.mark.timeout(600)
+def test_tv_4files_both_traversals_full(capsys):
+    """Term vector of the 4-file 10^8-token corpus by the bottom-up and the
+    top-down traversal and by the selector's choice (top-down here), in the
+    calls the traversal-choice benchmark times: the grammar loaded from
+    device tensors, one term-vector call per strategy. Every row against the
+    oracle's brute-force term vector of the uncompressed text, and the
+    inverted index of the selector's term vector against the oracle's."""
+    import torch
+    import paper_2106_06889_amd as gt
+    with capsys.disabled():
+        c, g = synth.workload("tv-4files")
+    F, T, V = g.num_files, len(c.tokens), g.vocab
+    R, S = g.num_rules, len(g.sym)
+    assert F == 4
+    w_off, w_word, w_cnt = oracle.tv_text(c.tokens, c.file_off, V)
+    del c
+    nnz = int(w_off[-1])
+    dev = torch.device("cuda", 0)
+    ro = torch.from_numpy(g.rule_off).to(dev)
+    sym = torch.from_numpy(g.sym).to(dev)
+    fo = torch.from_numpy(g.file_off).to(dev)
+    ctx = gt.Context(128 * R + 72 * S + 80 * V + 48 * T // 10 + (4 << 30))
+    try:
+        G = ctx.load(ro, sym, fo, V, borrow=True)
+        assert G.stats["tokens"] == T
+        assert G.tv_strategy() == gt.TV_TOP_DOWN
+        for strat in (gt.TV_BOTTOM_UP, gt.TV_TOP_DOWN, None):
+            tv = G.term_vector() if strat is None else G.term_vector(strat)
+            off = tv.arrays[0].cpu().numpy()
+            assert np.array_equal(off, w_off), strat
+            assert np.array_equal(tv.arrays[1][:nnz].cpu().numpy().view(np.uint32), w_word), strat
+            assert np.array_equal(gt.to_u64(tv.arrays[2])[:nnz], w_cnt), strat
+            if strat is None:
+                ii = G.inverted_index_from(tv)
+                i_off, i_file = oracle.inverted_index(w_off, w_word, V)
+                assert np.array_equal(ii.arrays[0].cpu().numpy(), i_off)
+                assert np.array_equal(ii.arrays[1][:nnz].cpu().numpy().view(np.uint32), i_file)
+                ii.free()
+            tv.free()
+        G.free()
+    finally:
+        ctx.close()
